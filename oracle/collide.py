@@ -1,0 +1,216 @@
+"""Local (per-node) collision operators (oracle; test infrastructure only).
+
+All functions act on a batch of n nodes: flow populations f (Q, n) -- full
+values, not deviations -- and scalar populations phi (P, n), float64.
+
+Order of operations inside one node (collide-then-stream form of Eq. 17):
+  1. moments: chi = sum phi (Eq. 27); rho = sum f (Eq. 19, compressible,
+     rho = 1 + delta rho as in Eq. 52-53); j = sum c f; Boussinesq force
+     F = g' chi e_g with e_g = (0,0,-1) (Eq. 11 in lattice units);
+     u = (j + F/2) / rho (Eq. 20).
+  2. Smagorinsky eddy viscosity from the pre-collision non-equilibrium stress
+     (Eq. 32-34, read in the standard form nu_T = (C_s Delta)^2 |S|,
+     |S| = sqrt(2 S:S), Delta = 1; tau_f solves the resulting quadratic
+     exactly) and the scalar diffusivity D0 + nu_T / Sc_T (Eq. 35).
+  3. flow collision: BGK with Guo forcing (Eq. 21-26) or cumulant (Eq. 54-58).
+  4. scalar BGK (Eq. 28-29) with the velocity of step 1.
+"""
+import math
+
+import torch
+
+from . import ring
+
+
+def _c(lat):
+    return lat.c.T.contiguous()          # (3, Q)
+
+
+def macroscopic(f, phi, P, extra_force=None):
+    """Eq. 18-20, 27 and 11. Returns rho (n,), j (3,n), chi (n,), F (3,n), u (3,n)."""
+    c = _c(P.flow)
+    rho = f.sum(0)
+    j = c @ f
+    chi = phi.sum(0)
+    F = torch.zeros_like(j)
+    F[2] = -P.g_prime * chi
+    bf = P.cfg.body_force
+    for a in range(3):
+        if bf[a] != 0.0:
+            F[a] = F[a] + bf[a]
+    u = (j + 0.5 * F) / rho
+    return rho, j, chi, F, u
+
+
+def smagorinsky_tau(pi_neq, rho, P, cs_smag):
+    """Total relaxation time tau_f from the non-equilibrium stress (3,3,n).
+
+    tau_f = (tau0 + sqrt(tau0^2 + 18 sqrt(2) C_s^2 sqrt(Q) / rho)) / 2,
+    Q = Pi:Pi. This is the root of tau^2 - tau0 tau - 3 C_s^2 |S| tau = 0 with
+    |S| tau = 3 sqrt(2 Q) / (2 rho) (strain from the stress, S = -Pi/(2 rho cs^2
+    tau)), i.e. nu_T = (C_s)^2 |S| and tau_f = tau0 + 3 nu_T (Eq. 25, 32-34).
+    The square root of Q uses a zero subgradient at Q = 0.
+    """
+    if cs_smag == 0.0:
+        return torch.full_like(rho, P.tau0)
+    Q = (pi_neq * pi_neq).sum((0, 1))
+    pos = Q > 0
+    sq = torch.where(pos, torch.sqrt(torch.where(pos, Q, torch.ones_like(Q))),
+                     torch.zeros_like(Q))
+    return 0.5 * (P.tau0 + torch.sqrt(P.tau0 ** 2 + 18.0 * math.sqrt(2.0) * cs_smag ** 2 * sq / rho))
+
+
+def scalar_tau(tau_f, P, sc_t):
+    """tau_phi = 1/2 + (D0 + nu_T / Sc_T) / cs_phi^2 with nu_T = (tau_f - tau0) cs^2
+    (Eq. 30, 35 read as adding the turbulent diffusivity to D0)."""
+    nu_t = (tau_f - P.tau0) * P.flow.cs2
+    return 0.5 + (P.d0 + nu_t / sc_t) / P.scal.cs2
+
+
+def feq_q19(rho, u, lat):
+    """Second-order equilibrium, Eq. 22 (any lattice with cs^2 = 1/3)."""
+    cu = _c(lat).T @ u                   # (Q, n)
+    uu = (u * u).sum(0)
+    cs2 = lat.cs2
+    return lat.w[:, None] * rho[None] * (1 + cu / cs2 + cu * cu / (2 * cs2 ** 2) - uu / (2 * cs2))
+
+
+def guo_source(u, F, tau, lat):
+    """Eq. 26: (1 - 1/(2 tau)) w [ (c - u)/cs^2 + (c.u) c / cs^4 ] . F"""
+    c = _c(lat)
+    cs2 = lat.cs2
+    cF = c.T @ F
+    cu = c.T @ u
+    uF = (u * F).sum(0)
+    return (1 - 0.5 / tau)[None] * lat.w[:, None] * ((cF - uF[None]) / cs2 + cu * cF / cs2 ** 2)
+
+
+def collide_bgk(f, rho, u, F, P, cs_smag):
+    """BGK + Guo (Eq. 21-26) with Smagorinsky tau (Eq. 32-34).
+    Pi_neq = sum_q c c (f - f_eq) (Eq. 33, outer product)."""
+    lat = P.flow
+    feq = feq_q19(rho, u, lat)
+    c = _c(lat)
+    fneq = f - feq
+    pi = torch.einsum('aq,bq,qn->abn', c, c, fneq)
+    tau = smagorinsky_tau(pi, rho, P, cs_smag)
+    fstar = f - (f - feq) / tau[None] + guo_source(u, F, tau, lat)
+    return fstar, tau
+
+
+def central_moments(f, u, lat):
+    """kappa_abc = sum_q (c_x - u_x)^a (c_y - u_y)^b (c_z - u_z)^c f_q,
+    a, b, c in {0,1,2} (Eq. 39 applied to f). Returns (3,3,3,n)."""
+    kappa = torch.zeros(3, 3, 3, f.shape[1], dtype=f.dtype)
+    for q, (cx, cy, cz) in enumerate(lat.c_list):
+        dx, dy, dz = cx - u[0], cy - u[1], cz - u[2]
+        px = torch.stack([torch.ones_like(dx), dx, dx * dx])
+        py = torch.stack([torch.ones_like(dy), dy, dy * dy])
+        pz = torch.stack([torch.ones_like(dz), dz, dz * dz])
+        kappa = kappa + px[:, None, None] * py[None, :, None] * pz[None, None, :] * f[q]
+    return kappa
+
+
+def raw_moments(f, lat):
+    """m_abc = sum_q c_x^a c_y^b c_z^c f_q, a, b, c in {0,1,2} (Eq. 18). (3,3,3,n)"""
+    m = torch.zeros(3, 3, 3, f.shape[1], dtype=f.dtype)
+    for q, c in enumerate(lat.c_list):
+        for a in range(3):
+            for b in range(3):
+                for cc in range(3):
+                    if (c[0] == 0 and a > 0) or (c[1] == 0 and b > 0) or (c[2] == 0 and cc > 0):
+                        continue
+                    m[a, b, cc] = m[a, b, cc] + (c[0] ** a) * (c[1] ** b) * (c[2] ** cc) * f[q]
+    return m
+
+
+def populations_from_raw(m, lat):
+    """Inverse of raw_moments: f = M0^{-1} m, M0[abc, q] = c_x^a c_y^b c_z^c
+    (nonsingular on D3Q27)."""
+    c = lat.c
+    M0 = torch.stack([c[:, 0] ** a * c[:, 1] ** b * c[:, 2] ** cc
+                      for a in range(3) for b in range(3) for cc in range(3)])  # (27, Q)
+    return torch.linalg.inv(M0) @ m.reshape(27, m.shape[-1])
+
+
+def collide_cumulant(f, rho, j, F, P, cs_smag):
+    """Cumulant collision on D3Q27 (Eq. 54-58).
+
+    a. cumulants of f / rho from the logarithm of its moment generating
+       function (Eq. 54), taken on the raw moments; the first-order cumulants
+       are the mean velocity j / rho (Eq. 57) and every cumulant of order >= 2
+       is independent of the frame;
+    b. LES: Pi_neq = rho (C_ab - delta_ab / 3) from the second-order cumulants;
+    c. relaxation C* = (1 - w) C + w C_eq (Eq. 55): the deviatoric second-order
+       cumulants C_110, C_101, C_011, C_200 - C_020, C_200 - C_002 with
+       w1 = 1/tau_f (Eq. 58) towards 0; the trace C_200 + C_020 + C_002 with
+       omega_bulk towards 1 (= 3 cs^2); every cumulant of order 3..6 with
+       omega3..omega6 towards 0;
+    d. density is conserved (Eq. 56) and the force enters the first-order
+       cumulants: C*_1 = (j + F) / rho, so that sum c f* = j + F (Eq. 17);
+    e. back through exp and the inverse of the moment map.
+    """
+    lat = P.flow
+    cfg = P.cfg
+    m = raw_moments(f, lat) / rho
+    C = ring.cumulants_from_moments(m)
+    idx2 = {(0, 0): (2, 0, 0), (1, 1): (0, 2, 0), (2, 2): (0, 0, 2),
+            (0, 1): (1, 1, 0), (0, 2): (1, 0, 1), (1, 2): (0, 1, 1)}
+    pi = torch.zeros(3, 3, f.shape[1], dtype=f.dtype)
+    for (a, b), (i, jj, k) in idx2.items():
+        v = rho * (C[i, jj, k] - (1.0 / 3.0 if a == b else 0.0))
+        pi[a, b] = v
+        pi[b, a] = v
+    tau = smagorinsky_tau(pi, rho, P, cs_smag)
+    w1 = 1.0 / tau
+    w2 = cfg.omega_bulk
+    Cs = C.clone()
+    cxx, cyy, czz = C[2, 0, 0], C[0, 2, 0], C[0, 0, 2]
+    dxy = (1 - w1) * (cxx - cyy)
+    dxz = (1 - w1) * (cxx - czz)
+    tr = (1 - w2) * (cxx + cyy + czz) + w2 * 1.0
+    Cs[2, 0, 0] = (tr + dxy + dxz) / 3.0
+    Cs[0, 2, 0] = (tr - 2.0 * dxy + dxz) / 3.0
+    Cs[0, 0, 2] = (tr + dxy - 2.0 * dxz) / 3.0
+    Cs[1, 1, 0] = (1 - w1) * C[1, 1, 0]
+    Cs[1, 0, 1] = (1 - w1) * C[1, 0, 1]
+    Cs[0, 1, 1] = (1 - w1) * C[0, 1, 1]
+    rates = {3: cfg.omega3, 4: cfg.omega4, 5: cfg.omega5, 6: cfg.omega6}
+    for i in range(3):
+        for jj in range(3):
+            for k in range(3):
+                o = i + jj + k
+                if o >= 3:
+                    Cs[i, jj, k] = (1 - rates[o]) * C[i, jj, k]
+    js = j + F
+    Cs[1, 0, 0] = js[0] / rho
+    Cs[0, 1, 0] = js[1] / rho
+    Cs[0, 0, 1] = js[2] / rho
+    fstar = populations_from_raw(ring.moments_from_cumulants(Cs) * rho, lat)
+    return fstar, tau
+
+
+def collide_scalar(phi, chi, u, tau_phi, P):
+    """Eq. 28-29: phi* = phi - (phi - w chi (1 + c.u / cs_phi^2)) / tau_phi.
+    Reading: cs_phi^2 is the scalar lattice's own sound speed squared (1/3 for
+    D3Q6 as printed, 1/4 for D3Q7) so that sum c phi_eq = chi u."""
+    lat = P.scal
+    cu = _c(lat).T @ u
+    peq = lat.w[:, None] * chi[None] * (1 + cu / lat.cs2)
+    return phi - (phi - peq) / tau_phi[None]
+
+
+def collide(f, phi, P, cs_smag=None, sc_t=None):
+    """One full local collision. cs_smag / sc_t may be tensors (for autograd)
+    or None to take them from the configuration. Returns (f*, phi*)."""
+    cfg = P.cfg
+    cs = cfg.cs_smag if cs_smag is None else cs_smag
+    sct = cfg.sc_t if sc_t is None else sc_t
+    rho, j, chi, F, u = macroscopic(f, phi, P)
+    if cfg.model == 0:
+        fstar, tau = collide_cumulant(f, rho, j, F, P, cs)
+    else:
+        fstar, tau = collide_bgk(f, rho, u, F, P, cs)
+    tau_phi = scalar_tau(tau, P, sct)
+    phistar = collide_scalar(phi, chi, u, tau_phi, P)
+    return fstar, phistar

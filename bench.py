@@ -1,0 +1,185 @@
+"""Throughput of the fused stream-and-collide step on one MI355X.
+
+Headline workload: the lock exchange on 1024 x 64 x 128 nodes, D3Q27 cumulant
+collision + D3Q7 scalar, Re_b = 30000, Smagorinsky C_s = 0.1, Sc_T = 1,
+g' = 1e-4, FP32 storage and arithmetic (synthetic initial state: step
+function in the concentration with seeded +-1e-3 noise at the gate). A step
+is one launch of the fused kernel over every node. Also measured on the same
+GPU: FP16 / BF16 storage of the same model on 2048 x 128 x 256 nodes, and
+the D3Q19 BGK + Smagorinsky + D3Q6 model on the headline grid.
+
+Timing: W warm-up steps, then K steps between HIP events recorded on the
+stream the kernels run on (torch's current stream, handed to the library).
+MNUPS = nodes * K / seconds / 1e6. Algorithmic HBM bytes per node update:
+one read and one write of every population, 2 * Q * bytes (272 B for the
+cumulant model in FP32). The oracle (FP64, CPU) is timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "cumulant27_q7_1024x64x128_fp32": dict(nx=1024, ny=64, nz=128, model=0, storage="f32"),
+    "bgk19_smag_q6_1024x64x128_fp32": dict(nx=1024, ny=64, nz=128, model=1, storage="f32"),
+    "cumulant27_q7_2048x128x256_fp32": dict(nx=2048, ny=128, nz=256, model=0, storage="f32"),
+    "cumulant27_q7_2048x128x256_fp16": dict(nx=2048, ny=128, nz=256, model=0, storage="f16"),
+    "cumulant27_q7_2048x128x256_bf16": dict(nx=2048, ny=128, nz=256, model=0, storage="bf16"),
+    "cumulant27_q7_4096x256x512_fp16": dict(nx=4096, ny=256, nz=512, model=0, storage="f16"),
+    "cumulant27_q7_4096x256x512_bf16": dict(nx=4096, ny=256, nz=512, model=0, storage="bf16"),
+}
+HEADLINE = "cumulant27_q7_1024x64x128_fp32"
+VARIANTS = ["cumulant27_q7_2048x128x256_fp16", "cumulant27_q7_2048x128x256_bf16",
+            "bgk19_smag_q6_1024x64x128_fp32"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2112_08479_amd", "csrc")
+    for n in ("lattice.h", "collide.h", "kernels.hip"):
+        with open(os.path.join(d, n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measure(name, steps, warmup):
+    import torch
+
+    import paper_2112_08479_amd as pkg
+    w = WORKLOADS[name]
+    st = {"f64": pkg.F64, "f32": pkg.F32, "f16": pkg.F16, "bf16": pkg.BF16}[w["storage"]]
+    cfg = pkg.Config(w["nx"], w["ny"], w["nz"], model=w["model"], storage=st, re_b=30000.0,
+                     g_prime=1e-4, cs_smag=0.1, sc_t=1.0)
+    lat = pkg.Lattice(cfg)
+    lat.init_lock_exchange(0.125, 1e-3, 0)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    lat.step(steps)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    d = lat.diagnostics(raise_unstable=False)
+    q = lat.params["q_flow"] + lat.params["q_scalar"]
+    es = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[w["storage"]]
+    bpn = 2 * q * es
+    n = cfg.n
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    mnups = n * steps / (ms * 1e-3) / 1e6
+    gbs = mnups * 1e6 * bpn / 1e9
+    return {"workload": name, "nodes": n, "steps": steps, "ms_per_step": ms / steps,
+            "MNUPS": mnups, "bytes_per_node_update": bpn, "GB_per_s": gbs,
+            "hbm_frac": gbs / HBM_PEAK_GBS, "nonfinite": d["nonfinite"], "mass_drift":
+            (d["mass"] - d["mass0"]) / d["mass0"], "x_f_nd": d["x_f_nd"]}
+
+
+def traffic_for(name, bpn_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as fh:
+        rec = json.load(fh).get(name)
+    if not rec or rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(budget_s=15.0):
+    """The FP64 oracle on a 1024 x 64 x 8 slab of the headline workload (the
+    same physical parameters, lock-exchange initial state), stepped until
+    about budget_s seconds have elapsed."""
+    import torch
+
+    from oracle import lbm as olbm
+    from oracle.params import Config as OConfig
+    from oracle.params import derive
+    torch.set_num_threads(os.cpu_count() or 1)
+    cores = torch.get_num_threads()
+    full = OConfig(1024, 64, 128, model=0, re_b=30000.0, cs_smag=0.1)
+    P = derive(full)
+    slab = OConfig(1024, 64, 8, model=0, re_b=30000.0, cs_smag=0.1)
+    f, phi = olbm.init_state(P, olbm.chi0_lock_exchange(slab, 0.125, 1e-3, 0))
+    n = slab.nx * slab.ny * slab.nz
+    t0 = time.time()
+    k = 0
+    while True:
+        f, phi = olbm.step(f, phi, P)
+        k += 1
+        if time.time() - t0 > budget_s or k >= 50:
+            break
+    dt = time.time() - t0
+    return {"value": n * k / dt / 1e6, "unit": "MNUPS", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle, {k} steps of a 1024x64x8 slab (z-layers of the "
+                      f"1024x64x128 workload, same parameters), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default=HEADLINE, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    head = measure(args.workload, args.steps, args.warmup)
+    print(json.dumps({"progress": "headline", **head}), file=sys.stderr, flush=True)
+    variants = []
+    if not args.no_variants:
+        for v in VARIANTS:
+            if v == args.workload:
+                continue
+            r = measure(v, max(50, args.steps // 4), min(args.warmup, 50))
+            print(json.dumps({"progress": "variant", **r}), file=sys.stderr, flush=True)
+            variants.append(r)
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+    launch_bytes = head["bytes_per_node_update"] * head["nodes"]
+    achieved = launch_bytes / (head["ms_per_step"] * 1e-3) / 1e9
+    w = WORKLOADS[args.workload]
+    line = {
+        "metric": "MNUPS (node updates per second / 1e6) of the fused stream-and-collide step",
+        "value": head["MNUPS"],
+        "unit": "MNUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32",
+                  "f64": "f64"}[w["storage"]],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "nx": w["nx"], "ny": w["ny"], "nz": w["nz"],
+                   "model": ["cumulant27_q7", "bgk19_smag_q6"][w["model"]], "re_b": 30000.0,
+                   "cs_smag": 0.1, "sc_t": 1.0, "g_prime": 1e-4, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_for(args.workload, launch_bytes)},
+        "cpu_baseline": cpu,
+        "variants": variants,
+        "paper_context": {"RAFSINE_D3Q19_BGK_D3Q6_V100_MNUPS": 1307,
+                          "VirtualFluids_D3Q27_cumulant_FCM_V100_MNUPS": 1064},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

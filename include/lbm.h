@@ -1,0 +1,184 @@
+/*
+ * lbm.h -- C ABI of the MI355X lock-exchange lattice Boltzmann library.
+ *
+ * Method: Adekanye et al., "GPU accelerated lattice Boltzmann method
+ * simulations of dilute gravity currents" (arXiv 2112.08479). One time step
+ * is the collide-then-stream update of Eq. 17 for the flow populations and
+ * Eq. 28 for the scalar populations, coupled through the Boussinesq force of
+ * Eq. 11, with half-way bounce-back walls (no slip, no flux) at x = 0, x = nx,
+ * z = 0, z = nz and a periodic span y (Sec. 2.5).
+ *
+ *   model LBM_CUMULANT27_Q7 : D3Q27 cumulant collision (Eq. 36, 54-58) and a
+ *                             D3Q7 BGK scalar (Eq. 28-30 on D3Q6 + rest)
+ *   model LBM_BGK19_SMAG_Q6 : D3Q19 BGK + Guo forcing (Eq. 21-26) with
+ *                             Smagorinsky eddy viscosity (Eq. 32-35) and a
+ *                             D3Q6 BGK scalar (Eq. 28-31)
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns 0 (LBM_OK) or a negative LBM_E* code and never
+ *     throws across the ABI; lbm_last_error() gives a thread-local message
+ *     for the last failure on the calling thread.
+ *   - Device memory is owned by the caller. lbm_create carves its buffers out
+ *     of a caller workspace; the handle owns only host memory. All pointers
+ *     named *_dev are device pointers, host_* are host pointers.
+ *   - Work is queued on the caller's HIP stream in order. Only
+ *     lbm_diagnostics, lbm_get_populations, lbm_set_populations,
+ *     lbm_checkpoint_load and lbm_adjoint_run synchronise that stream.
+ *   - Node (i, j, k) has linear index i + nx (j + ny k); x = i is the
+ *     streamwise direction, y = j the span, z = k the vertical (gravity
+ *     along -z, Eq. 10). Population arrays use the layout
+ *     [population][k][j][i] (structure of arrays, i fastest).
+ *   - Population order (for the get/set hooks): D3Q19 in the order printed
+ *     in Eq. 23; D3Q27 = that list followed by the corners (1,1,1),
+ *     (-1,-1,-1), (1,1,-1), (-1,-1,1), (1,-1,1), (-1,1,-1), (1,-1,-1),
+ *     (-1,1,1); D3Q6 in the order of Eq. 31; D3Q7 = rest + D3Q6.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,    /* invalid argument or configuration */
+  LBM_ENOMEM = -2,    /* workspace or slot too small */
+  LBM_EDEVICE = -3,   /* a HIP runtime call failed */
+  LBM_ENODEV = -4,    /* no GPU visible */
+  LBM_EUNSTABLE = -5, /* the state holds non-finite values */
+  LBM_ESTATE = -6     /* call out of order (e.g. step before init) */
+};
+
+enum { LBM_CUMULANT27_Q7 = 0, LBM_BGK19_SMAG_Q6 = 1 };
+
+/* Storage type of the populations. The flow populations are stored as
+ * deviations f_q - w_q from the lattice rest state (the split of Eq. 52-53),
+ * the scalar populations as raw values. Arithmetic is FP64 when the storage
+ * is LBM_F64 and FP32 otherwise; global reductions are FP64. 16-bit stores
+ * round to nearest even. */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3 };
+
+/* Output element type for lbm_moments. */
+enum { LBM_OUT_F32 = 1, LBM_OUT_F64 = 0 };
+
+typedef struct {
+  uint32_t struct_size;   /* must be sizeof(lbm_config) */
+  int32_t nx, ny, nz;     /* nodes; depth H = nz lattice units */
+  int32_t model;          /* LBM_CUMULANT27_Q7 or LBM_BGK19_SMAG_Q6 */
+  int32_t storage;        /* LBM_F64 / LBM_F32 / LBM_F16 / LBM_BF16 */
+  double re_b;            /* buoyancy Reynolds number U_b H / nu0 (Eq. 12-14) */
+  double sc;              /* Schmidt number nu0 / D0 */
+  double g_prime;         /* reduced gravity, lattice units */
+  double ub_lu;           /* > 0: U_b in lattice units, g' = ub_lu^2 / nz
+                             (the paper's convention U_b = 0.03, Sec. 2.5) */
+  double cs_smag;         /* Smagorinsky constant C_s; 0 disables the LES */
+  double sc_t;            /* turbulent Schmidt number */
+  double omega_bulk;      /* cumulant trace (bulk) relaxation rate, (0, 2) */
+  double omega3, omega4, omega5, omega6; /* cumulant rates of order 3..6 */
+} lbm_config;
+
+/* Derived lattice-unit parameters (Sec. 2.5, Eq. 25, 30). */
+typedef struct {
+  double u_b;       /* sqrt(g' H) */
+  double g_prime;
+  double nu0;       /* U_b H / Re_b */
+  double tau0;      /* 3 nu0 + 1/2 */
+  double d0;        /* nu0 / Sc */
+  double tau_phi0;  /* 1/2 + D0 / cs_phi^2 */
+  double cs2_phi;   /* 1/4 (D3Q7) or 1/3 (D3Q6) */
+  int32_t q_flow, q_scalar;
+} lbm_params;
+
+/* Diagnostics of the state at the current step (pre-collision moments):
+ *   mass = sum rho, chi_mass = sum chi (mass0 / chi_mass0: at initialisation);
+ *   fw = sum over the bottom layer of nu0 (9 u_x(z=0) - u_x(z=1)) / 3
+ *        (Eq. 62 with the half-way wall, Eq. 64), fw_nd = fw / (U_b^2 H^2);
+ *   x_front: front position from the span-averaged concentration with
+ *        threshold 0.02 (Sec. 3.1), linearly interpolated between node
+ *        centres; x_f = x_front - x0 (gate position); x_f_nd = x_f / H;
+ *   umax = max |u|; nonfinite = nodes whose rho, u or chi is not finite;
+ *   t_nd = step U_b / H. */
+typedef struct {
+  int64_t step;
+  double t_nd, mass, mass0, chi_mass, chi_mass0, fw, fw_nd;
+  double x_front, x_f, x_f_nd, umax;
+  int64_t nonfinite;
+} lbm_diag;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Host only. Fills *out from cfg (Sec. 2.5). LBM_EINVAL if cfg is invalid
+ * (sizes < 1 or nx*ny*nz >= 2^31, unknown model/storage, Re_b, Sc, Sc_T <= 0,
+ * g' < 0, tau0 <= 1/2, rates outside (0, 2), C_s < 0). */
+int lbm_derive_params(const lbm_config* cfg, lbm_params* out);
+
+/* Host only. Device workspace bytes lbm_create needs for cfg: two population
+ * buffers (read / write) plus reduction scratch. 0 if cfg is invalid. */
+size_t lbm_workspace_bytes(const lbm_config* cfg);
+
+/* Host only. Bytes of one checkpoint slot: one population buffer + step. */
+size_t lbm_state_bytes(const lbm_config* cfg);
+
+/* Validates cfg (LBM_EINVAL, before any device work), checks for a GPU
+ * (LBM_ENODEV) and the workspace size (LBM_ENOMEM), then builds a handle on
+ * the current device. dev_workspace: caller-owned device memory of at least
+ * lbm_workspace_bytes(cfg) bytes, 256-byte aligned, kept alive until
+ * lbm_destroy. hip_stream: hipStream_t (NULL = default stream). */
+int lbm_create(const lbm_config* cfg, void* dev_workspace, size_t bytes,
+               void* hip_stream, lbm_handle** out);
+
+/* Frees the handle (host memory only; never the caller's workspace). */
+int lbm_destroy(lbm_handle* h);
+
+/* Initial state of Sec. 2.5 at step 0: zero momentum (f = w), chi0 = 1 for
+ * i < floor(lock_fraction nx), else 0, plus noise_amp (2U - 1) in the two
+ * columns i = floor(lock_fraction nx) - 1 and floor(lock_fraction nx), with
+ * U = (splitmix64(seed ^ (l * 0x9E3779B97F4A7C15)) >> 11) 2^-53 and l the
+ * node's linear index; phi = w_phi chi0. Records mass0 and chi_mass0. */
+int lbm_init_lock_exchange(lbm_handle* h, double lock_fraction, double noise_amp,
+                           uint64_t seed);
+
+/* Same with chi0 given as nx*ny*nz doubles in device memory (layout above);
+ * lock_fraction only sets the gate position x0 used by the front diagnostic. */
+int lbm_init_from_field(lbm_handle* h, const double* chi0_dev, double lock_fraction);
+
+/* Queues n time steps (Eq. 17, 28). n = 0 is a no-op; n < 0 is LBM_EINVAL;
+ * LBM_ESTATE before initialisation. Does not synchronise. */
+int lbm_step(lbm_handle* h, int64_t n);
+
+/* Pre-collision moments of the current state (Eq. 19-20, 27): rho, the
+ * velocity u = (j + F/2)/rho, chi, nx*ny*nz elements each of type dtype
+ * (LBM_OUT_F32 / LBM_OUT_F64) into caller device buffers; NULL skips one. */
+int lbm_moments(lbm_handle* h, int dtype, void* rho_dev, void* ux_dev,
+                void* uy_dev, void* uz_dev, void* chi_dev);
+
+/* Computes the diagnostics (FP64 reductions on the GPU), synchronises and
+ * writes *out. Returns LBM_EUNSTABLE (with *out filled) if nonfinite > 0. */
+int lbm_diagnostics(lbm_handle* h, lbm_diag* out);
+
+/* Step counter of the handle. */
+int lbm_get_step(const lbm_handle* h, int64_t* step);
+
+/* Copies the population buffer and the step counter into a caller device
+ * slot of lbm_state_bytes(cfg) bytes (asynchronous). */
+int lbm_checkpoint_save(lbm_handle* h, void* dev_slot);
+/* Restores a slot written by lbm_checkpoint_save for the same configuration
+ * (synchronises to read the step counter back). */
+int lbm_checkpoint_load(lbm_handle* h, const void* dev_slot);
+
+/* Test hooks. Pre-collision populations at the current step as full values
+ * (f, not f - w), float64, host arrays of q_flow*N and q_scalar*N in the
+ * population order above. Synchronous. */
+int lbm_get_populations(lbm_handle* h, double* host_f, double* host_phi);
+int lbm_set_populations(lbm_handle* h, const double* host_f, const double* host_phi);
+
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,360 @@
+// C ABI: validation, parameter derivation (Sec. 2.5), workspace layout, step
+// loop and host orchestration. Every entry point returns an LBM_E* code and
+// records a message retrievable with lbm_last_error().
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "runtime.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHECK(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(LBM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));           \
+  } while (0)
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t storage_bytes(int storage) {
+  switch (storage) {
+    case LBM_F64: return 8;
+    case LBM_F32: return 4;
+    case LBM_F16: return 2;
+    case LBM_BF16: return 2;
+  }
+  return 0;
+}
+
+struct Layout {
+  size_t buf, chibar, partials, dres, d0, scratch, total;
+  int diag_blocks;
+};
+
+int block_x(int nx) { return nx >= lbm::kBlock ? lbm::kBlock : ((nx + 63) / 64) * 64; }
+
+Layout layout_of(const lbm_config* c, const lbm_params* p) {
+  Layout L;
+  const int64_t n = (int64_t)c->nx * c->ny * c->nz;
+  const int qt = p->q_flow + p->q_scalar;
+  const int nbx = (c->nx + block_x(c->nx) - 1) / block_x(c->nx);
+  L.diag_blocks = nbx * c->nz;
+  size_t off = 0;
+  L.buf = align256((size_t)qt * n * storage_bytes(c->storage));
+  L.chibar = 2 * L.buf;
+  off = L.chibar + align256((size_t)c->nx * c->nz * sizeof(double));
+  L.partials = off;
+  off += align256((size_t)L.diag_blocks * lbm::kDiagSlots * sizeof(double));
+  L.dres = off;
+  off += 256;
+  L.d0 = off;
+  off += 256;
+  L.scratch = off;
+  off += align256((size_t)n * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+int validate(const lbm_config* c, lbm_params* out) {
+  if (!c) return fail(LBM_EINVAL, "config is NULL");
+  if (c->struct_size != sizeof(lbm_config))
+    return fail(LBM_EINVAL, "config struct_size %u != %zu", c->struct_size, sizeof(lbm_config));
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1)
+    return fail(LBM_EINVAL, "grid %d x %d x %d: every size must be >= 1", c->nx, c->ny, c->nz);
+  const int64_t n = (int64_t)c->nx * c->ny * c->nz;
+  if (n >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "grid has %lld nodes (limit 2^31 - 1)", (long long)n);
+  if (c->model != LBM_CUMULANT27_Q7 && c->model != LBM_BGK19_SMAG_Q6)
+    return fail(LBM_EINVAL, "unknown model %d", c->model);
+  if (storage_bytes(c->storage) == 0) return fail(LBM_EINVAL, "unknown storage %d", c->storage);
+  if (!(c->re_b > 0) || !(c->sc > 0) || !(c->sc_t > 0))
+    return fail(LBM_EINVAL, "Re_b, Sc and Sc_T must be > 0");
+  if (!(c->g_prime >= 0) || !(c->ub_lu >= 0) || !(c->cs_smag >= 0))
+    return fail(LBM_EINVAL, "g', ub_lu and C_s must be >= 0");
+  const double rates[5] = {c->omega_bulk, c->omega3, c->omega4, c->omega5, c->omega6};
+  for (double r : rates)
+    if (!(r > 0 && r < 2)) return fail(LBM_EINVAL, "relaxation rates must lie in (0, 2)");
+  lbm_params p;
+  const double H = (double)c->nz;
+  p.g_prime = c->ub_lu > 0 ? c->ub_lu * c->ub_lu / H : c->g_prime;
+  p.u_b = sqrt(p.g_prime * H);
+  p.nu0 = p.u_b * H / c->re_b;
+  p.tau0 = 3.0 * p.nu0 + 0.5;
+  p.d0 = p.nu0 / c->sc;
+  p.cs2_phi = c->model == LBM_CUMULANT27_Q7 ? 0.25 : 1.0 / 3.0;
+  p.tau_phi0 = 0.5 + p.d0 / p.cs2_phi;
+  p.q_flow = c->model == LBM_CUMULANT27_Q7 ? 27 : 19;
+  p.q_scalar = c->model == LBM_CUMULANT27_Q7 ? 7 : 6;
+  if (!(p.tau0 > 0.5))
+    return fail(LBM_EINVAL, "tau0 = %.17g must be > 1/2 (g' = 0 or Re_b too large)", p.tau0);
+  if (out) *out = p;
+  return LBM_OK;
+}
+
+int require_ready(lbm_handle* h) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!h->initialised) return fail(LBM_ESTATE, "state not initialised (call lbm_init_*)");
+  return LBM_OK;
+}
+
+int set_device(lbm_handle* h) {
+  HIPCHECK(hipSetDevice(h->device));
+  return LBM_OK;
+}
+
+int run_diag(lbm_handle* h, double* dst) {
+  HIPCHECK(lbm::launch_diag(h, dst));
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err; }
+
+int lbm_derive_params(const lbm_config* cfg, lbm_params* out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  return validate(cfg, out);
+}
+
+size_t lbm_workspace_bytes(const lbm_config* cfg) {
+  lbm_params p;
+  if (validate(cfg, &p) != LBM_OK) return 0;
+  return layout_of(cfg, &p).total;
+}
+
+size_t lbm_state_bytes(const lbm_config* cfg) {
+  lbm_params p;
+  if (validate(cfg, &p) != LBM_OK) return 0;
+  return layout_of(cfg, &p).buf + 256;
+}
+
+int lbm_create(const lbm_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
+               lbm_handle** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  lbm_params p;
+  int rc = validate(cfg, &p);
+  if (rc) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(LBM_ENODEV, "no GPU visible to the HIP runtime");
+  if (!dev_workspace) return fail(LBM_EINVAL, "workspace is NULL");
+  if (((uintptr_t)dev_workspace & 255) != 0) return fail(LBM_EINVAL, "workspace not 256-byte aligned");
+  const Layout L = layout_of(cfg, &p);
+  if (bytes < L.total)
+    return fail(LBM_ENOMEM, "workspace of %zu bytes, %zu needed", bytes, L.total);
+  lbm_handle* h = new (std::nothrow) lbm_handle();
+  if (!h) return fail(LBM_ENOMEM, "host allocation failed");
+  h->cfg = *cfg;
+  h->prm = p;
+  h->qf = p.q_flow;
+  h->qs = p.q_scalar;
+  h->qt = p.q_flow + p.q_scalar;
+  h->n = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+  h->esize = storage_bytes(cfg->storage);
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(LBM_EDEVICE, "hipGetDevice failed");
+  }
+  h->stream = (hipStream_t)hip_stream;
+  h->ws = (char*)dev_workspace;
+  h->ws_bytes = bytes;
+  h->buf[0] = h->ws;
+  h->buf[1] = h->ws + L.buf;
+  h->cur = 0;
+  h->chibar = (double*)(h->ws + L.chibar);
+  h->partials = (double*)(h->ws + L.partials);
+  h->dres = (double*)(h->ws + L.dres);
+  h->d0 = (double*)(h->ws + L.d0);
+  h->scratch = (double*)(h->ws + L.scratch);
+  h->diag_blocks = L.diag_blocks;
+  h->step = 0;
+  h->initialised = false;
+  h->x0 = (int)floor(0.125 * cfg->nx);
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_handle* h) {
+  delete h;
+  return LBM_OK;
+}
+
+static int after_init(lbm_handle* h) {
+  h->step = 0;
+  h->initialised = true;
+  return run_diag(h, h->d0);
+}
+
+int lbm_init_lock_exchange(lbm_handle* h, double lock_fraction, double noise_amp, uint64_t seed) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!(lock_fraction > 0 && lock_fraction < 1)) return fail(LBM_EINVAL, "lock_fraction must be in (0, 1)");
+  if (!(noise_amp >= 0 && noise_amp < 1)) return fail(LBM_EINVAL, "noise_amp must be in [0, 1)");
+  int rc = set_device(h);
+  if (rc) return rc;
+  h->cur = 0;
+  h->x0 = (int)floor(lock_fraction * h->cfg.nx);
+  HIPCHECK(lbm::launch_init_lock(h, lock_fraction, noise_amp, seed));
+  return after_init(h);
+}
+
+int lbm_init_from_field(lbm_handle* h, const double* chi0_dev, double lock_fraction) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!chi0_dev) return fail(LBM_EINVAL, "chi0 is NULL");
+  if (!(lock_fraction >= 0 && lock_fraction < 1)) return fail(LBM_EINVAL, "lock_fraction must be in [0, 1)");
+  int rc = set_device(h);
+  if (rc) return rc;
+  h->cur = 0;
+  h->x0 = (int)floor(lock_fraction * h->cfg.nx);
+  HIPCHECK(lbm::launch_init_field(h, chi0_dev));
+  return after_init(h);
+}
+
+int lbm_step(lbm_handle* h, int64_t n) {
+  int rc = require_ready(h);
+  if (rc) return rc;
+  if (n < 0) return fail(LBM_EINVAL, "negative step count");
+  if (n == 0) return LBM_OK;
+  rc = set_device(h);
+  if (rc) return rc;
+  for (int64_t i = 0; i < n; ++i) {
+    HIPCHECK(lbm::launch_step(h, h->buf[h->cur], h->buf[h->cur ^ 1]));
+    h->cur ^= 1;
+    h->step += 1;
+  }
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_handle* h, int dtype, void* rho, void* ux, void* uy, void* uz, void* chi) {
+  int rc = require_ready(h);
+  if (rc) return rc;
+  if (dtype != LBM_OUT_F32 && dtype != LBM_OUT_F64) return fail(LBM_EINVAL, "dtype must be LBM_OUT_F32 or LBM_OUT_F64");
+  rc = set_device(h);
+  if (rc) return rc;
+  HIPCHECK(lbm::launch_moments(h, dtype, rho, ux, uy, uz, chi));
+  return LBM_OK;
+}
+
+int lbm_get_step(const lbm_handle* h, int64_t* step) {
+  if (!h || !step) return fail(LBM_EINVAL, "NULL argument");
+  *step = h->step;
+  return LBM_OK;
+}
+
+int lbm_diagnostics(lbm_handle* h, lbm_diag* out) {
+  int rc = require_ready(h);
+  if (rc) return rc;
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  rc = set_device(h);
+  if (rc) return rc;
+  rc = run_diag(h, h->dres);
+  if (rc) return rc;
+  double r[8], r0[8];
+  HIPCHECK(hipMemcpyAsync(r, h->dres, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipMemcpyAsync(r0, h->d0, sizeof(r0), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  const double H = (double)h->cfg.nz, ub = h->prm.u_b;
+  out->step = h->step;
+  out->t_nd = (double)h->step * ub / H;
+  out->mass = r[0];
+  out->mass0 = r0[0];
+  out->chi_mass = r[1];
+  out->chi_mass0 = r0[1];
+  out->fw = r[2];
+  out->fw_nd = ub > 0 ? r[2] / (ub * ub * H * H) : 0.0;
+  out->x_front = r[3];
+  out->x_f = r[3] - h->x0;
+  out->x_f_nd = out->x_f / H;
+  out->umax = r[4];
+  out->nonfinite = (int64_t)r[5];
+  if (out->nonfinite > 0)
+    return fail(LBM_EUNSTABLE, "%lld nodes hold non-finite moments at step %lld",
+                (long long)out->nonfinite, (long long)h->step);
+  return LBM_OK;
+}
+
+int lbm_checkpoint_save(lbm_handle* h, void* dev_slot) {
+  int rc = require_ready(h);
+  if (rc) return rc;
+  if (!dev_slot) return fail(LBM_EINVAL, "slot is NULL");
+  rc = set_device(h);
+  if (rc) return rc;
+  const size_t sb = (size_t)h->qt * h->n * h->esize;
+  HIPCHECK(lbm::launch_copy_state(h, h->buf[h->cur], dev_slot));
+  // the step counter follows the populations (256-byte aligned)
+  static thread_local int64_t stepbuf;
+  stepbuf = h->step;
+  HIPCHECK(hipMemcpyAsync((char*)dev_slot + align256(sb), &stepbuf, sizeof(int64_t),
+                          hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_checkpoint_load(lbm_handle* h, const void* dev_slot) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!dev_slot) return fail(LBM_EINVAL, "slot is NULL");
+  int rc = set_device(h);
+  if (rc) return rc;
+  const size_t sb = (size_t)h->qt * h->n * h->esize;
+  HIPCHECK(lbm::launch_copy_state(h, dev_slot, h->buf[h->cur]));
+  int64_t s = 0;
+  HIPCHECK(hipMemcpyAsync(&s, (const char*)dev_slot + align256(sb), sizeof(int64_t),
+                          hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  h->step = s;
+  h->initialised = true;
+  return LBM_OK;
+}
+
+int lbm_get_populations(lbm_handle* h, double* host_f, double* host_phi) {
+  int rc = require_ready(h);
+  if (rc) return rc;
+  if (!host_f || !host_phi) return fail(LBM_EINVAL, "NULL output");
+  rc = set_device(h);
+  if (rc) return rc;
+  for (int a = 0; a < h->qt; ++a) {
+    double* dst = a < h->qf ? host_f + (int64_t)a * h->n : host_phi + (int64_t)(a - h->qf) * h->n;
+    HIPCHECK(lbm::launch_get_pop(h, a, h->scratch));
+    HIPCHECK(hipMemcpyAsync(dst, h->scratch, h->n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_set_populations(lbm_handle* h, const double* host_f, const double* host_phi) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!host_f || !host_phi) return fail(LBM_EINVAL, "NULL input");
+  int rc = set_device(h);
+  if (rc) return rc;
+  for (int a = 0; a < h->qt; ++a) {
+    const double* srcp = a < h->qf ? host_f + (int64_t)a * h->n : host_phi + (int64_t)(a - h->qf) * h->n;
+    HIPCHECK(hipMemcpyAsync(h->scratch, srcp, h->n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(lbm::launch_set_pop(h, a, h->scratch));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+  }
+  if (!h->initialised) {
+    h->step = 0;
+    h->initialised = true;
+    return run_diag(h, h->d0);
+  }
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,586 @@
+// Forward kernels: fused gather + collide + store step, initial states,
+// moment export, FP64 diagnostics, test hooks.
+//
+// State convention. A population buffer holds post-collision values at the
+// node where they were produced. One step pulls them (the gather with
+// half-way bounce-back and periodic span, i.e. streaming of Eq. 17), collides
+// at the node and writes the result to the other buffer. The pre-collision
+// populations at step n are therefore gather(buffer). The gather is a
+// permutation of the (population, node) slots, so every state has exactly one
+// buffer representation; the init kernels and the set hook write the inverse
+// permutation.
+#include <math.h>
+
+#include "collide.h"
+#include "lattice.h"
+#include "runtime.h"
+
+namespace lbm {
+
+template <int MODEL>
+struct ModelT;
+template <>
+struct ModelT<0> {
+  using LF = Q27;
+  using LS = Q7;
+};
+template <>
+struct ModelT<1> {
+  using LF = Q19;
+  using LS = Q6;
+};
+
+template <typename T>
+LBM_HD double to_d(T v);
+template <>
+LBM_HD double to_d<double>(double v) { return v; }
+template <>
+LBM_HD double to_d<float>(float v) { return (double)v; }
+
+template <typename ST>
+__device__ __forceinline__ void store_val(ST* p, ST v) {
+  *p = v;
+}
+
+// ------------------------------------------------------------------- step
+template <int MODEL, typename ST, typename CT, bool LES, bool GEN>
+__global__ __launch_bounds__(kBlock) void k_step(const ST* __restrict__ src, ST* __restrict__ dst,
+                                                 Grid g, Phys<CT> p, int nbx) {
+  using LF = typename ModelT<MODEL>::LF;
+  using LS = typename ModelT<MODEL>::LS;
+  const int b = blockIdx.x;
+  const int row = b / nbx;
+  const int x = (b - row * nbx) * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t node = (int64_t)row * g.nx + x;
+  CT fg[LF::Q], ph[LS::Q];
+  gather<LF, LS, ST, CT>(src, g, x, y, z, node, fg, ph);
+  if constexpr (MODEL == 0) {
+    if constexpr (GEN)
+      collide_cumulant_q27_q7_general<LES, CT>(fg, ph, p);
+    else
+      collide_cumulant_q27_q7<LES, CT>(fg, ph, p);
+  } else {
+    collide_bgk_q19_q6<LES, CT>(fg, ph, p);
+  }
+  static_for<0, LF::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    store_val(dst + (int64_t)q * g.n + node, Conv<ST, CT>::store(fg[q]));
+  });
+  static_for<0, LS::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    store_val(dst + (int64_t)(LF::Q + q) * g.n + node, Conv<ST, CT>::store(ph[q]));
+  });
+}
+
+// ------------------------------------------------------------ init states
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+struct LockInit {
+  int gate;
+  double amp;
+  uint64_t seed;
+  __device__ double chi0(const Grid& g, int i, int j, int k) const {
+    double c = (i < gate) ? 1.0 : 0.0;
+    if (amp != 0.0 && (i == gate - 1 || i == gate)) {
+      const uint64_t lin = (uint64_t)i + (uint64_t)g.nx * ((uint64_t)j + (uint64_t)g.ny * (uint64_t)k);
+      const uint64_t r = splitmix64(seed ^ (lin * 0x9E3779B97F4A7C15ull));
+      const double U = (double)(r >> 11) * 0x1.0p-53;
+      c += amp * (2.0 * U - 1.0);
+    }
+    return c;
+  }
+};
+struct FieldInit {
+  const double* chi;
+  __device__ double chi0(const Grid& g, int i, int j, int k) const {
+    return chi[((int64_t)k * g.ny + j) * g.nx + i];
+  }
+};
+
+// Buffer slot (q, node) is read by node + c_q when that node is fluid, else by
+// the node itself for population opp(q) (bounce-back). Initial populations:
+// flow f = w (stored deviation 0), scalar phi_p = w_p chi0.
+template <int MODEL, typename ST, class Init>
+__global__ __launch_bounds__(kBlock) void k_init(ST* __restrict__ dst, Grid g, Init init, int nbx) {
+  using LF = typename ModelT<MODEL>::LF;
+  using LS = typename ModelT<MODEL>::LS;
+  using CT = typename std::conditional<std::is_same<ST, double>::value, double, float>::type;
+  const int b = blockIdx.x;
+  const int row = b / nbx;
+  const int x = (b - row * nbx) * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t node = (int64_t)row * g.nx + x;
+  static_for<0, LF::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    dst[(int64_t)q * g.n + node] = Conv<ST, CT>::store(CT(0));
+  });
+  static_for<0, LS::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    const int xn = x + LS::cx[q], zn = z + LS::cz[q];
+    int yn = y + LS::cy[q];
+    yn = yn < 0 ? g.ny - 1 : (yn >= g.ny ? 0 : yn);
+    const bool fluid = (unsigned)xn < (unsigned)g.nx && (unsigned)zn < (unsigned)g.nz;
+    const double c = fluid ? init.chi0(g, xn, yn, zn) : init.chi0(g, x, y, z);
+    dst[(int64_t)(LF::Q + q) * g.n + node] = Conv<ST, CT>::store(CT(weight<LS>(q) * c));
+  });
+}
+
+// ----------------------------------------------------------------- moments
+template <typename OT>
+__device__ __forceinline__ void put_out(void* p, int64_t i, double v) {
+  if (p) static_cast<OT*>(p)[i] = (OT)v;
+}
+
+template <int MODEL, typename ST, typename CT, typename OT>
+__global__ __launch_bounds__(kBlock) void k_moments(const ST* __restrict__ src, Grid g, double gp,
+                                                    int nbx, void* rho, void* ux, void* uy,
+                                                    void* uz, void* chi) {
+  using LF = typename ModelT<MODEL>::LF;
+  using LS = typename ModelT<MODEL>::LS;
+  const int b = blockIdx.x;
+  const int row = b / nbx;
+  const int x = (b - row * nbx) * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t node = (int64_t)row * g.nx + x;
+  CT fg[LF::Q], ph[LS::Q];
+  gather<LF, LS, ST, CT>(src, g, x, y, z, node, fg, ph);
+  double drho = 0, jx = 0, jy = 0, jz = 0, c = 0;
+  static_for<0, LF::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    const double v = to_d(fg[q]);
+    drho += v;
+    if (LF::cx[q]) jx += LF::cx[q] * v;
+    if (LF::cy[q]) jy += LF::cy[q] * v;
+    if (LF::cz[q]) jz += LF::cz[q] * v;
+  });
+  static_for<0, LS::Q>([&](auto qc) { c += to_d(ph[decltype(qc)::value]); });
+  const double r = 1.0 + drho;
+  put_out<OT>(rho, node, r);
+  put_out<OT>(ux, node, jx / r);
+  put_out<OT>(uy, node, jy / r);
+  put_out<OT>(uz, node, (jz - 0.5 * gp * c) / r);
+  put_out<OT>(chi, node, c);
+}
+
+// ------------------------------------------------------------- diagnostics
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// block-wide reduction of NV values (sum, except index imax: max); result in
+// thread 0. Fixed order, so the result is reproducible.
+template <int NV>
+__device__ void block_reduce(double (&v)[NV], int imax) {
+  __shared__ double red[kBlock / 64 * NV];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = (k == imax) ? wave_max(v[k]) : wave_sum(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[wid * NV + k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < nw; ++w)
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+        v[k] = (k == imax) ? fmax(v[k], red[w * NV + k]) : v[k] + red[w * NV + k];
+  }
+  __syncthreads();
+}
+
+// one thread per (x, z) column, looping over the span
+template <int MODEL, typename ST, typename CT>
+__global__ __launch_bounds__(kBlock) void k_diag_columns(const ST* __restrict__ src, Grid g,
+                                                         double gp, double* __restrict__ chibar,
+                                                         double* __restrict__ partials, int nbx) {
+  using LF = typename ModelT<MODEL>::LF;
+  using LS = typename ModelT<MODEL>::LS;
+  const int z = blockIdx.x / nbx;
+  const int x = (blockIdx.x - z * nbx) * blockDim.x + threadIdx.x;
+  double v[6] = {0, 0, 0, 0, 0, 0};  // drho, chi, u_x(z=0), u_x(z=1), umax, nonfinite
+  if (x < g.nx) {
+    double col = 0;
+    for (int y = 0; y < g.ny; ++y) {
+      const int64_t node = ((int64_t)z * g.ny + y) * g.nx + x;
+      CT fg[LF::Q], ph[LS::Q];
+      gather<LF, LS, ST, CT>(src, g, x, y, z, node, fg, ph);
+      double drho = 0, jx = 0, jy = 0, jz = 0, c = 0;
+      static_for<0, LF::Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const double t = to_d(fg[q]);
+        drho += t;
+        if (LF::cx[q]) jx += LF::cx[q] * t;
+        if (LF::cy[q]) jy += LF::cy[q] * t;
+        if (LF::cz[q]) jz += LF::cz[q] * t;
+      });
+      static_for<0, LS::Q>([&](auto qc) { c += to_d(ph[decltype(qc)::value]); });
+      const double r = 1.0 + drho;
+      const double ux = jx / r, uy = jy / r, uz = (jz - 0.5 * gp * c) / r;
+      const bool fin = isfinite(r) && isfinite(c) && isfinite(ux) && isfinite(uy) && isfinite(uz);
+      v[0] += drho;
+      col += c;
+      if (z == 0) v[2] += ux;
+      if (z == 1) v[3] += ux;
+      if (fin)
+        v[4] = fmax(v[4], sqrt(ux * ux + uy * uy + uz * uz));
+      else
+        v[5] += 1.0;
+    }
+    v[1] = col;
+    chibar[(int64_t)z * g.nx + x] = col / g.ny;
+  }
+  block_reduce<6>(v, 4);
+  if (threadIdx.x == 0) {
+    double* o = partials + (int64_t)blockIdx.x * kDiagSlots;
+    for (int k = 0; k < 6; ++k) o[k] = v[k];
+  }
+}
+
+// single block: reduce the partials, locate the front, write out[8] =
+// {mass, chi_mass, fw, x_front, umax, nonfinite, i_star, 0}
+__global__ __launch_bounds__(1024) void k_diag_final(const double* __restrict__ partials, int nparts,
+                                                     const double* __restrict__ chibar, Grid g,
+                                                     double nu0, double* __restrict__ out) {
+  __shared__ double red[16 * 6];
+  __shared__ int ired[16];
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  double v[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = t; b < nparts; b += blockDim.x) {
+    const double* p = partials + (int64_t)b * kDiagSlots;
+    for (int k = 0; k < 6; ++k) v[k] = (k == 4) ? fmax(v[k], p[k]) : v[k] + p[k];
+  }
+  const double theta = 0.02;
+  int best = -1;
+  for (int i = t; i < g.nx; i += blockDim.x) {
+    double m = -INFINITY;
+    for (int k = 0; k < g.nz; ++k) m = fmax(m, chibar[(int64_t)k * g.nx + i]);
+    if (m >= theta) best = i;
+  }
+  for (int k = 0; k < 6; ++k) v[k] = (k == 4) ? wave_max(v[k]) : wave_sum(v[k]);
+  for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
+  if (lane == 0) {
+    for (int k = 0; k < 6; ++k) red[wid * 6 + k] = v[k];
+    ired[wid] = best;
+  }
+  __syncthreads();
+  if (t == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int w = 1; w < nw; ++w) {
+      for (int k = 0; k < 6; ++k) v[k] = (k == 4) ? fmax(v[k], red[w * 6 + k]) : v[k] + red[w * 6 + k];
+      best = max(best, ired[w]);
+    }
+    double xf;
+    if (best < 0) {
+      xf = 0.0;
+    } else if (best == g.nx - 1) {
+      xf = (double)g.nx;
+    } else {
+      double m0 = -INFINITY, m1 = -INFINITY;
+      for (int k = 0; k < g.nz; ++k) {
+        m0 = fmax(m0, chibar[(int64_t)k * g.nx + best]);
+        m1 = fmax(m1, chibar[(int64_t)k * g.nx + best + 1]);
+      }
+      xf = best + 0.5 + (m0 - theta) / (m0 - m1);
+    }
+    out[0] = (double)g.n + v[0];
+    out[1] = v[1];
+    out[2] = g.nz >= 2 ? nu0 * (9.0 * v[2] - v[3]) / 3.0 : 0.0;
+    out[3] = xf;
+    out[4] = v[4];
+    out[5] = v[5];
+    out[6] = (double)best;
+    out[7] = 0.0;
+  }
+}
+
+// -------------------------------------------------------------- test hooks
+template <class L>
+__device__ __forceinline__ void vel(int q, int& cx, int& cy, int& cz) {
+  cx = L::cx[q];
+  cy = L::cy[q];
+  cz = L::cz[q];
+}
+
+// pre-collision population a (0..qt-1) at every node, full value, float64
+template <int MODEL, typename ST>
+__global__ __launch_bounds__(kBlock) void k_get_pop(const ST* __restrict__ src, Grid g, int a,
+                                                    int nbx, double* __restrict__ out) {
+  using LF = typename ModelT<MODEL>::LF;
+  using LS = typename ModelT<MODEL>::LS;
+  using CT = typename std::conditional<std::is_same<ST, double>::value, double, float>::type;
+  const int b = blockIdx.x;
+  const int row = b / nbx;
+  const int x = (b - row * nbx) * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t node = (int64_t)row * g.nx + x;
+  const bool flow = a < LF::Q;
+  const int q = flow ? a : a - LF::Q;
+  int cx, cy, cz, o;
+  double w;
+  if (flow) {
+    vel<LF>(q, cx, cy, cz);
+    o = opp<LF>(q);
+    w = weight<LF>(q);
+  } else {
+    vel<LS>(q, cx, cy, cz);
+    o = opp<LS>(q);
+    w = 0.0;
+  }
+  const int base = flow ? 0 : LF::Q;
+  const int xs = x - cx, zs = z - cz;
+  int ys = y - cy;
+  ys = ys < 0 ? g.ny - 1 : (ys >= g.ny ? 0 : ys);
+  const bool wall = (unsigned)xs >= (unsigned)g.nx || (unsigned)zs >= (unsigned)g.nz;
+  const int64_t off = wall ? (int64_t)(base + o) * g.n + node
+                           : (int64_t)(base + q) * g.n + ((int64_t)zs * g.ny + ys) * g.nx + xs;
+  out[node] = to_d(Conv<ST, CT>::load(src[off])) + w;
+}
+
+// inverse of the gather for population a given its pre-collision values v
+// (full values, float64): slot (a, y) <- v(y + c_a) when that node is fluid;
+// slot (opp a, y) <- v(y) when y - c_a is outside.
+template <int MODEL, typename ST>
+__global__ __launch_bounds__(kBlock) void k_set_pop(ST* __restrict__ dst, Grid g, int a, int nbx,
+                                                    const double* __restrict__ v) {
+  using LF = typename ModelT<MODEL>::LF;
+  using LS = typename ModelT<MODEL>::LS;
+  using CT = typename std::conditional<std::is_same<ST, double>::value, double, float>::type;
+  const int b = blockIdx.x;
+  const int row = b / nbx;
+  const int x = (b - row * nbx) * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  const int y = row % g.ny, z = row / g.ny;
+  const int64_t node = (int64_t)row * g.nx + x;
+  const bool flow = a < LF::Q;
+  const int q = flow ? a : a - LF::Q;
+  int cx, cy, cz, o;
+  double w;
+  if (flow) {
+    vel<LF>(q, cx, cy, cz);
+    o = opp<LF>(q);
+    w = weight<LF>(q);
+  } else {
+    vel<LS>(q, cx, cy, cz);
+    o = opp<LS>(q);
+    w = 0.0;
+  }
+  const int base = flow ? 0 : LF::Q;
+  {
+    const int xn = x + cx, zn = z + cz;
+    int yn = y + cy;
+    yn = yn < 0 ? g.ny - 1 : (yn >= g.ny ? 0 : yn);
+    if ((unsigned)xn < (unsigned)g.nx && (unsigned)zn < (unsigned)g.nz)
+      dst[(int64_t)(base + q) * g.n + node] =
+          Conv<ST, CT>::store(CT(v[((int64_t)zn * g.ny + yn) * g.nx + xn] - w));
+  }
+  {
+    const int xs = x - cx, zs = z - cz;
+    if ((unsigned)xs >= (unsigned)g.nx || (unsigned)zs >= (unsigned)g.nz)
+      dst[(int64_t)(base + o) * g.n + node] = Conv<ST, CT>::store(CT(v[node] - w));
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+static Grid grid_of(const lbm_handle* h) { return Grid{h->cfg.nx, h->cfg.ny, h->cfg.nz, h->n}; }
+
+static int block_x(const lbm_handle* h) {
+  const int nx = h->cfg.nx;
+  return nx >= kBlock ? kBlock : ((nx + 63) / 64) * 64;
+}
+
+template <typename CT>
+static Phys<CT> phys_of(const lbm_handle* h) {
+  const lbm_params& p = h->prm;
+  const lbm_config& c = h->cfg;
+  Phys<CT> r;
+  r.g = (CT)p.g_prime;
+  r.tau0 = (CT)p.tau0;
+  r.tau_phi0 = (CT)p.tau_phi0;
+  r.c_les = (CT)(18.0 * sqrt(2.0) * c.cs_smag * c.cs_smag);
+  r.d0 = (CT)p.d0;
+  r.inv_sct = (CT)(1.0 / c.sc_t);
+  r.inv_cs2phi = (CT)(1.0 / p.cs2_phi);
+  r.omega2 = (CT)c.omega_bulk;
+  r.omega3 = (CT)c.omega3;
+  r.omega4 = (CT)c.omega4;
+  r.omega5 = (CT)c.omega5;
+  r.omega6 = (CT)c.omega6;
+  return r;
+}
+
+// calls f(ST{}, CT{}) for the handle's storage type
+template <class F>
+static hipError_t with_storage(const lbm_handle* h, F&& f) {
+  switch (h->cfg.storage) {
+    case LBM_F64: return f(double{}, double{});
+    case LBM_F32: return f(float{}, float{});
+    case LBM_F16: return f(__half{}, float{});
+    case LBM_BF16: return f(bf16_t{}, float{});
+  }
+  return hipErrorInvalidValue;
+}
+template <class F>
+static hipError_t with_model(const lbm_handle* h, F&& f) {
+  if (h->cfg.model == 0) return f(std::integral_constant<int, 0>{});
+  return f(std::integral_constant<int, 1>{});
+}
+
+static bool general_rates(const lbm_handle* h) {
+  const lbm_config& c = h->cfg;
+  return c.omega3 != 1.0 || c.omega4 != 1.0 || c.omega5 != 1.0 || c.omega6 != 1.0;
+}
+
+hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
+  const Grid g = grid_of(h);
+  const int bx = block_x(h);
+  const int nbx = (g.nx + bx - 1) / bx;
+  const unsigned blocks = (unsigned)((int64_t)nbx * g.ny * g.nz);
+  const bool les = h->cfg.cs_smag > 0.0;
+  const bool gen = general_rates(h);
+  return with_model(h, [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    return with_storage(h, [&](auto st, auto ct) {
+      using ST = decltype(st);
+      using CT = decltype(ct);
+      const Phys<CT> p = phys_of<CT>(h);
+      const ST* s = static_cast<const ST*>(src);
+      ST* d = static_cast<ST*>(dst);
+      if (les) {
+        if (M == 0 && gen)
+          hipLaunchKernelGGL((k_step<M, ST, CT, true, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx);
+        else
+          hipLaunchKernelGGL((k_step<M, ST, CT, true, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx);
+      } else {
+        if (M == 0 && gen)
+          hipLaunchKernelGGL((k_step<M, ST, CT, false, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx);
+        else
+          hipLaunchKernelGGL((k_step<M, ST, CT, false, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx);
+      }
+      return hipGetLastError();
+    });
+  });
+}
+
+template <class Init>
+static hipError_t launch_init_any(lbm_handle* h, Init init) {
+  const Grid g = grid_of(h);
+  const int bx = block_x(h);
+  const int nbx = (g.nx + bx - 1) / bx;
+  const unsigned blocks = (unsigned)((int64_t)nbx * g.ny * g.nz);
+  return with_model(h, [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    return with_storage(h, [&](auto st, auto) {
+      using ST = decltype(st);
+      hipLaunchKernelGGL((k_init<M, ST, Init>), dim3(blocks), dim3(bx), 0, h->stream,
+                         static_cast<ST*>(h->buf[h->cur]), g, init, nbx);
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t launch_init_lock(lbm_handle* h, double lock_fraction, double amp, uint64_t seed) {
+  LockInit init{(int)floor(lock_fraction * h->cfg.nx), amp, seed};
+  return launch_init_any(h, init);
+}
+
+hipError_t launch_init_field(lbm_handle* h, const double* chi0) {
+  return launch_init_any(h, FieldInit{chi0});
+}
+
+hipError_t launch_moments(lbm_handle* h, int dtype, void* rho, void* ux, void* uy, void* uz,
+                          void* chi) {
+  const Grid g = grid_of(h);
+  const int bx = block_x(h);
+  const int nbx = (g.nx + bx - 1) / bx;
+  const unsigned blocks = (unsigned)((int64_t)nbx * g.ny * g.nz);
+  const double gp = h->prm.g_prime;
+  return with_model(h, [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    return with_storage(h, [&](auto st, auto ct) {
+      using ST = decltype(st);
+      using CT = decltype(ct);
+      const ST* s = static_cast<const ST*>(h->buf[h->cur]);
+      if (dtype == LBM_OUT_F64)
+        hipLaunchKernelGGL((k_moments<M, ST, CT, double>), dim3(blocks), dim3(bx), 0, h->stream, s, g, gp, nbx, rho, ux, uy, uz, chi);
+      else
+        hipLaunchKernelGGL((k_moments<M, ST, CT, float>), dim3(blocks), dim3(bx), 0, h->stream, s, g, gp, nbx, rho, ux, uy, uz, chi);
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t launch_diag(lbm_handle* h, double* out) {
+  const Grid g = grid_of(h);
+  const int bx = block_x(h);
+  const int nbx = (g.nx + bx - 1) / bx;
+  const double gp = h->prm.g_prime;
+  hipError_t e = with_model(h, [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    return with_storage(h, [&](auto st, auto ct) {
+      using ST = decltype(st);
+      using CT = decltype(ct);
+      hipLaunchKernelGGL((k_diag_columns<M, ST, CT>), dim3(nbx * g.nz), dim3(bx), 0, h->stream,
+                         static_cast<const ST*>(h->buf[h->cur]), g, gp, h->chibar, h->partials,
+                         nbx);
+      return hipGetLastError();
+    });
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(1024), 0, h->stream, h->partials, nbx * g.nz,
+                     h->chibar, g, h->prm.nu0, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_pop(lbm_handle* h, int a, double* dst) {
+  const Grid g = grid_of(h);
+  const int bx = block_x(h);
+  const int nbx = (g.nx + bx - 1) / bx;
+  const unsigned blocks = (unsigned)((int64_t)nbx * g.ny * g.nz);
+  return with_model(h, [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    return with_storage(h, [&](auto st, auto) {
+      using ST = decltype(st);
+      hipLaunchKernelGGL((k_get_pop<M, ST>), dim3(blocks), dim3(bx), 0, h->stream,
+                         static_cast<const ST*>(h->buf[h->cur]), g, a, nbx, dst);
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t launch_set_pop(lbm_handle* h, int a, const double* src) {
+  const Grid g = grid_of(h);
+  const int bx = block_x(h);
+  const int nbx = (g.nx + bx - 1) / bx;
+  const unsigned blocks = (unsigned)((int64_t)nbx * g.ny * g.nz);
+  return with_model(h, [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    return with_storage(h, [&](auto st, auto) {
+      using ST = decltype(st);
+      hipLaunchKernelGGL((k_set_pop<M, ST>), dim3(blocks), dim3(bx), 0, h->stream,
+                         static_cast<ST*>(h->buf[h->cur]), g, a, nbx, src);
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t launch_copy_state(lbm_handle* h, const void* src, void* dst) {
+  return hipMemcpyAsync(dst, src, (size_t)h->qt * h->n * h->esize, hipMemcpyDeviceToDevice,
+                        h->stream);
+}
+
+}  // namespace lbm

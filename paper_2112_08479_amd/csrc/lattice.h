@@ -1,0 +1,175 @@
+// Velocity sets, weights, storage conversions and the pull gather with
+// half-way bounce-back used by every kernel of the library.
+//
+// Velocity sets: D3Q19 in the order of Eq. 23, D3Q27 = D3Q19 + the eight
+// corners (Eq. 36 lists only seven; (1,-1,1) is added), D3Q6 in the order of
+// Eq. 31, D3Q7 = rest + D3Q6. Moving velocities come in +/- pairs, so the
+// opposite of q is q+1 / q-1.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#define LBM_HD __host__ __device__ __forceinline__
+
+namespace lbm {
+
+struct Q27 {
+  static constexpr int Q = 27;
+  static constexpr bool has_rest = true;
+  static constexpr int cx[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                                 1, -1, 1, -1, 1, -1, 1, -1};
+  static constexpr int cy[27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                                 1, -1, 1, -1, -1, 1, -1, 1};
+  static constexpr int cz[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                                 1, -1, -1, 1, 1, -1, -1, 1};
+};
+struct Q19 {
+  static constexpr int Q = 19;
+  static constexpr bool has_rest = true;
+  static constexpr int cx[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int cy[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int cz[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+};
+struct Q7 {
+  static constexpr int Q = 7;
+  static constexpr bool has_rest = true;
+  static constexpr int cx[7] = {0, 1, -1, 0, 0, 0, 0};
+  static constexpr int cy[7] = {0, 0, 0, 1, -1, 0, 0};
+  static constexpr int cz[7] = {0, 0, 0, 0, 0, 1, -1};
+};
+struct Q6 {
+  static constexpr int Q = 6;
+  static constexpr bool has_rest = false;
+  static constexpr int cx[6] = {1, -1, 0, 0, 0, 0};
+  static constexpr int cy[6] = {0, 0, 1, -1, 0, 0};
+  static constexpr int cz[6] = {0, 0, 0, 0, 1, -1};
+};
+
+template <class L>
+constexpr int opp(int q) {
+  return L::has_rest ? (q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1)) : ((q & 1) ? q - 1 : q + 1);
+}
+
+// Weights. D3Q19 (Eq. 24): 1/3, 1/18, 1/36 by |c|^2 = 0, 1, 2. D3Q27: tensor
+// product of the one-dimensional weights 2/3 (c = 0) and 1/6 (c = +-1).
+// D3Q6: 1/6 (Eq. 31). D3Q7: 1/4 rest, 1/8 moving.
+template <class L>
+constexpr double weight(int q);
+template <>
+constexpr double weight<Q27>(int q) {
+  return (Q27::cx[q] ? 1.0 / 6.0 : 2.0 / 3.0) * (Q27::cy[q] ? 1.0 / 6.0 : 2.0 / 3.0) *
+         (Q27::cz[q] ? 1.0 / 6.0 : 2.0 / 3.0);
+}
+template <>
+constexpr double weight<Q19>(int q) {
+  return q == 0 ? 1.0 / 3.0 : (q < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+template <>
+constexpr double weight<Q7>(int q) {
+  return q == 0 ? 0.25 : 0.125;
+}
+template <>
+constexpr double weight<Q6>(int q) {
+  return 1.0 / 6.0;
+}
+
+// population index of velocity (a, b, c) in D3Q27
+constexpr int idx27(int a, int b, int c) {
+  for (int q = 0; q < 27; ++q)
+    if (Q27::cx[q] == a && Q27::cy[q] == b && Q27::cz[q] == c) return q;
+  return -1;
+}
+
+// ---------------------------------------------------------------- storage
+struct bf16_t {
+  uint16_t bits;
+};
+
+template <typename ST, typename CT>
+struct Conv;
+template <>
+struct Conv<double, double> {
+  static LBM_HD double load(double v) { return v; }
+  static LBM_HD double store(double v) { return v; }
+};
+template <>
+struct Conv<float, float> {
+  static LBM_HD float load(float v) { return v; }
+  static LBM_HD float store(float v) { return v; }
+};
+template <>
+struct Conv<__half, float> {
+  static LBM_HD float load(__half v) { return __half2float(v); }
+  static LBM_HD __half store(float v) { return __float2half_rn(v); }
+};
+template <>
+struct Conv<bf16_t, float> {
+  static LBM_HD float load(bf16_t v) {
+    uint32_t u = (uint32_t)v.bits << 16;
+    return __uint_as_float(u);
+  }
+  // round to nearest even on the 16 dropped bits; NaN stays NaN
+  static LBM_HD bf16_t store(float v) {
+    uint32_t u = __float_as_uint(v);
+    bf16_t r;
+    if ((u & 0x7fffffffu) > 0x7f800000u) {
+      r.bits = (uint16_t)((u >> 16) | 0x40u);
+    } else {
+      u += 0x7fffu + ((u >> 16) & 1u);
+      r.bits = (uint16_t)(u >> 16);
+    }
+    return r;
+  }
+};
+
+// ---------------------------------------------------------------- geometry
+struct Grid {
+  int nx, ny, nz;
+  int64_t n;  // nodes
+};
+
+// Source element (array index, node index) that population q of lattice L at
+// node (x, y, z) pulls from: the neighbour x - c_q when it is a fluid node
+// (y taken modulo ny), else -- half-way bounce-back -- population opp(q) of
+// the node itself.
+template <class L, int q>
+LBM_HD int64_t pull_offset(const Grid& g, int base, int x, int y, int z, int64_t node) {
+  constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
+  const int xs = x - cx;
+  const int zs = z - cz;
+  int ys = y - cy;
+  if (cy == 1) ys = (y == 0) ? g.ny - 1 : ys;
+  if (cy == -1) ys = (y == g.ny - 1) ? 0 : ys;
+  bool wall = false;
+  if (cx != 0) wall = wall || ((unsigned)xs >= (unsigned)g.nx);
+  if (cz != 0) wall = wall || ((unsigned)zs >= (unsigned)g.nz);
+  const int64_t src = ((int64_t)zs * g.ny + ys) * g.nx + xs;
+  return wall ? (int64_t)(base + opp<L>(q)) * g.n + node : (int64_t)(base + q) * g.n + src;
+}
+
+template <int I, int N, class F>
+LBM_HD void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// Gathers the pre-collision populations of node (x, y, z): flow populations
+// as deviations f - w into fg[], scalar populations into ph[].
+template <class LF, class LS, typename ST, typename CT>
+LBM_HD void gather(const ST* __restrict__ src, const Grid& g, int x, int y, int z, int64_t node,
+                   CT* fg, CT* ph) {
+  static_for<0, LF::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    fg[q] = Conv<ST, CT>::load(src[pull_offset<LF, q>(g, 0, x, y, z, node)]);
+  });
+  static_for<0, LS::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    ph[q] = Conv<ST, CT>::load(src[pull_offset<LS, q>(g, LF::Q, x, y, z, node)]);
+  });
+}
+
+}  // namespace lbm

@@ -1,0 +1,51 @@
+// Handle and launcher interface shared by the C ABI (abi.cpp) and the kernel
+// translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/lbm.h"
+
+struct lbm_handle {
+  lbm_config cfg;
+  lbm_params prm;
+  int qf, qs, qt;     // flow, scalar, total populations
+  int64_t n;          // nodes
+  size_t esize;       // bytes per stored population value
+  int device;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  void* buf[2];       // population buffers (post-collision values, pull layout)
+  int cur;            // index of the buffer holding the current state
+  double* chibar;     // nx * nz span sums of chi (diagnostics)
+  double* partials;   // per-block diagnostic partial sums
+  double* dres;       // 8 doubles: current diagnostics
+  double* d0;         // 8 doubles: diagnostics at initialisation
+  double* scratch;    // n doubles (get/set hooks)
+  int64_t step;
+  bool initialised;
+  int x0;             // gate index
+  int diag_blocks;
+};
+
+namespace lbm {
+
+constexpr int kBlock = 256;
+constexpr int kDiagSlots = 8;  // partial sums per diagnostic block
+
+// kernels.hip
+hipError_t launch_step(lbm_handle* h, const void* src, void* dst);
+hipError_t launch_init_lock(lbm_handle* h, double lock_fraction, double amp, uint64_t seed);
+hipError_t launch_init_field(lbm_handle* h, const double* chi0);
+hipError_t launch_moments(lbm_handle* h, int dtype, void* rho, void* ux, void* uy, void* uz,
+                          void* chi);
+hipError_t launch_diag(lbm_handle* h, double* out);
+hipError_t launch_get_pop(lbm_handle* h, int q, double* dst);
+hipError_t launch_set_pop(lbm_handle* h, int q, const double* src);
+hipError_t launch_copy_state(lbm_handle* h, const void* src, void* dst);
+
+}  // namespace lbm

@@ -1,0 +1,117 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and exports
+every function include/lbm.h declares, parameter derivation matches the
+oracle's, and invalid configurations fail with the documented codes before
+any device work."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_2112_08479_amd as pkg
+from oracle.params import Config as OConfig
+from oracle.params import derive
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "lbm.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_\w+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pkg.lib()
+    names = _declared()
+    assert names, "no declarations parsed"
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(pkg.EXPORTS) == names
+
+
+CONFIGS = [
+    dict(nx=128, ny=8, nz=16, model=0, re_b=1000.0),
+    dict(nx=1024, ny=64, nz=128, model=0, re_b=30000.0, cs_smag=0.1),
+    dict(nx=1024, ny=64, nz=128, model=1, re_b=30000.0, cs_smag=0.1),
+    dict(nx=256, ny=16, nz=32, model=0, re_b=1000.0, cs_smag=0.1),
+    dict(nx=4096, ny=256, nz=512, model=0, re_b=30000.0, cs_smag=0.1),
+    dict(nx=1500, ny=100, nz=100, model=1, re_b=1000.0, ub_lu=0.03),
+]
+
+
+@pytest.mark.parametrize("kw", CONFIGS)
+def test_derived_parameters_match_the_oracle(kw):
+    got = pkg.derive_params(pkg.Config(**kw))
+    P = derive(OConfig(**kw))
+    for k, want in (("u_b", P.u_b), ("g_prime", P.g_prime), ("nu0", P.nu0), ("tau0", P.tau0),
+                    ("d0", P.d0), ("tau_phi0", P.tau_phi0), ("cs2_phi", P.scal.cs2)):
+        assert math.isclose(got[k], want, rel_tol=1e-15), (k, got[k], want)
+    assert got["q_flow"] == P.flow.Q and got["q_scalar"] == P.scal.Q
+
+
+def test_workspace_bytes_cover_two_population_buffers():
+    for st, es in ((pkg.F64, 8), (pkg.F32, 4), (pkg.F16, 2), (pkg.BF16, 2)):
+        cfg = pkg.Config(1024, 64, 128, model=0, storage=st, re_b=30000.0)
+        nb = pkg.workspace_bytes(cfg)
+        assert nb >= 2 * 34 * cfg.n * es
+        assert nb < 2 * 34 * cfg.n * es + 8 * cfg.n + (1 << 22)
+    big = pkg.Config(4096, 256, 512, model=0, storage=pkg.F16, re_b=30000.0)
+    assert pkg.workspace_bytes(big) > 2 * 34 * big.n * 2          # 73 GB: needs 64-bit sizes
+
+
+BAD = [
+    (dict(nx=0, ny=8, nz=16), "size"),
+    (dict(nx=8, ny=-1, nz=16), "size"),
+    (dict(nx=2048, ny=1024, nz=1024), "2^31"),
+    (dict(nx=8, ny=8, nz=16, model=5), "model"),
+    (dict(nx=8, ny=8, nz=16, storage=9), "storage"),
+    (dict(nx=8, ny=8, nz=16, re_b=0.0), "Re_b"),
+    (dict(nx=8, ny=8, nz=16, sc_t=0.0), "Sc_T"),
+    (dict(nx=8, ny=8, nz=16, g_prime=0.0), "tau0"),
+    (dict(nx=8, ny=8, nz=16, g_prime=-1e-4), "g'"),
+    (dict(nx=8, ny=8, nz=16, cs_smag=-0.1), "C_s"),
+    (dict(nx=8, ny=8, nz=16, omega3=2.0), "rates"),
+    (dict(nx=8, ny=8, nz=16, omega_bulk=0.0), "rates"),
+]
+
+
+@pytest.mark.parametrize("kw,msg", BAD)
+def test_invalid_configurations_are_rejected(kw, msg):
+    cfg = pkg.Config(**kw)
+    assert pkg.workspace_bytes(cfg) == 0
+    with pytest.raises(pkg.LBMError) as e:
+        pkg.derive_params(cfg)
+    assert e.value.code == pkg.LBM_EINVAL
+    assert msg in str(e.value)
+    # lbm_create validates before touching the device
+    h = ctypes.c_void_p()
+    rc = pkg.lib().lbm_create(ctypes.byref(cfg.c()), ctypes.c_void_p(256), 1 << 20, None, ctypes.byref(h))
+    assert rc == pkg.LBM_EINVAL and not h.value
+
+
+def test_struct_size_is_checked():
+    c = pkg.Config(8, 8, 16).c()
+    c.struct_size = 8
+    assert pkg.lib().lbm_derive_params(ctypes.byref(c), ctypes.byref(pkg.c_params())) == pkg.LBM_EINVAL
+
+
+def test_create_without_a_gpu_reports_enodev():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    cfg = pkg.Config(8, 8, 16)
+    h = ctypes.c_void_p()
+    rc = pkg.lib().lbm_create(ctypes.byref(cfg.c()), ctypes.c_void_p(256), pkg.workspace_bytes(cfg),
+                              None, ctypes.byref(h))
+    assert rc == pkg.LBM_ENODEV
+    assert "GPU" in pkg.lib().lbm_last_error().decode()
+
+
+def test_null_handles_are_rejected():
+    L = pkg.lib()
+    assert L.lbm_step(None, 1) == pkg.LBM_EINVAL
+    assert L.lbm_diagnostics(None, None) == pkg.LBM_EINVAL
+    assert L.lbm_checkpoint_load(None, None) == pkg.LBM_EINVAL
+    assert L.lbm_destroy(None) == pkg.LBM_OK

@@ -1,0 +1,242 @@
+"""Parity of the HIP library (through the C ABI) with the FP64 oracle.
+
+Tolerances
+  FP64 storage : 1e-13 absolute on populations after one step, and moments
+                 within 1e-10 of the oracle field's infinity norm over 500
+                 steps of the 128x8x16 lock exchange.
+  FP32 storage : moments within 1e-5 over 100 steps (relative to each field's
+                 infinity norm); populations after one step within 2e-7.
+  FP16 / BF16  : one step from the same rounded state: the difference is at
+                 most the final rounding (half an ulp of the 16-bit format)
+                 plus FP32 arithmetic error.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2112_08479_amd as pkg
+from oracle import diag as odiag
+from oracle import lbm as olbm
+from tests import inputs
+from tests.gpu_helpers import both, gpu_moments, moment_errors, oracle_moments, ulp
+
+pytestmark = pytest.mark.gpu
+
+C0 = dict(nx=128, ny=8, nz=16, model=0, re_b=1000.0)
+
+
+def _oracle_run(P, cfg_kw, steps_at, seed=0):
+    from oracle.params import Config as OConfig
+    ocfg = OConfig(**{k: v for k, v in cfg_kw.items() if k in ("nx", "ny", "nz")})
+    f, phi = olbm.init_state(P, olbm.chi0_lock_exchange(ocfg, 0.125, 1e-3, seed))
+    out = {}
+    n = 0
+    for s in sorted(steps_at):
+        while n < s:
+            f, phi = olbm.step(f, phi, P)
+            n += 1
+        out[s] = (oracle_moments(f, phi, P), odiag.diagnostics(f, phi, P, s))
+    return out
+
+
+_cache = {}
+
+
+def oracle_trajectory(key, P, kw, steps):
+    if key not in _cache:
+        torch.set_num_threads(max(1, min(16, torch.get_num_threads())))
+        _cache[key] = _oracle_run(P, kw, steps)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_initial_state_matches_oracle_bitwise(model):
+    kw = dict(C0, model=model)
+    cfg, P = both(pkg.F64, **kw)
+    lat = pkg.Lattice(cfg)
+    lat.init_lock_exchange(0.125, 1e-3, 7)
+    f, phi = lat.get_populations()
+    from oracle.params import Config as OConfig
+    of, ophi = olbm.init_state(P, olbm.chi0_lock_exchange(OConfig(128, 8, 16), 0.125, 1e-3, 7))
+    assert np.array_equal(f, of.numpy())
+    assert np.array_equal(phi, ophi.numpy())
+
+
+def _random_case(model, storage, cs, rates, shape=(5, 3, 300), seed=1, eps=1e-2):
+    kw = dict(nx=shape[2], ny=shape[1], nz=shape[0], model=model, re_b=2000.0, g_prime=1e-3,
+              cs_smag=cs)
+    if rates is not None:
+        kw.update(omega_bulk=rates[0], omega3=rates[1], omega4=rates[2], omega5=rates[3], omega6=rates[4])
+    cfg, P = both(storage, **kw)
+    f, phi = inputs.near_rest_state(P.flow.Q, P.scal.Q, shape, P.flow.w.numpy(), P.scal.w.numpy(),
+                                    seed, eps=eps)
+    lat = pkg.Lattice(cfg)
+    lat.set_populations(f, phi)
+    f0, phi0 = lat.get_populations()          # the state as stored (rounded)
+    lat.step(1)
+    f1, phi1 = lat.get_populations()
+    of, ophi = olbm.step(torch.from_numpy(f0), torch.from_numpy(phi0), P)
+    return P, f0, phi0, f1, phi1, of.numpy(), ophi.numpy()
+
+
+CASES = [(0, 0.0, None), (0, 0.1, None), (0, 0.1, (1.2, 0.8, 1.3, 0.7, 1.6)), (1, 0.0, None),
+         (1, 0.1, None)]
+
+
+@pytest.mark.parametrize("model,cs,rates", CASES)
+@pytest.mark.parametrize("storage", [pkg.F64, pkg.F32])
+def test_one_step_from_random_state(model, cs, rates, storage):
+    P, f0, phi0, f1, phi1, of, ophi = _random_case(model, storage, cs, rates)
+    tol = 1e-13 if storage == pkg.F64 else 2e-7
+    assert np.abs(f1 - of).max() < tol
+    assert np.abs(phi1 - ophi).max() < tol
+
+
+@pytest.mark.parametrize("model,cs,rates", CASES)
+@pytest.mark.parametrize("storage,mant", [(pkg.F16, 10), (pkg.BF16, 7)])
+def test_one_step_16bit_storage(model, cs, rates, storage, mant):
+    P, f0, phi0, f1, phi1, of, ophi = _random_case(model, storage, cs, rates)
+    w = P.flow.w.numpy()[:, None, None, None]
+    g_got, g_want = f1 - w, of - w                    # stored quantity: f - w
+    assert np.all(np.abs(g_got - g_want) <= 0.5 * ulp(g_want, mant) + 2e-7)
+    assert np.all(np.abs(phi1 - ophi) <= 0.5 * ulp(ophi, mant) + 2e-7)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("model", [0, 1])
+def test_lock_exchange_fp64_500_steps(model):
+    """128x8x16 lock exchange, Re_b = 1000, no LES: moments within 1e-10."""
+    kw = dict(C0, model=model)
+    cfg, P = both(pkg.F64, **kw)
+    steps = (1, 10, 100, 500)
+    ref = oracle_trajectory(("c0", model), P, kw, steps)
+    lat = pkg.Lattice(cfg)
+    lat.init_lock_exchange(0.125, 1e-3, 0)
+    n = 0
+    for s in steps:
+        lat.step(s - n)
+        n = s
+        errs = moment_errors(gpu_moments(lat), ref[s][0])
+        print(f"model {model} step {s} errors {errs}", flush=True)
+        assert max(errs.values()) < 1e-10, (s, errs)
+        d, od = lat.diagnostics(), ref[s][1]
+        for k in ("mass", "chi_mass", "x_front", "x_f"):
+            assert abs(d[k] - od[k]) <= 1e-9 * max(1.0, abs(od[k])), (s, k, d[k], od[k])
+        assert abs(d["fw"] - od["fw"]) <= 1e-9 * max(abs(od["fw"]), 1e-12), (s, d["fw"], od["fw"])
+        assert abs(d["umax"] - od["umax"]) <= 1e-9 * od["umax"]
+        assert d["nonfinite"] == 0 and d["step"] == s
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("model", [0, 1])
+def test_lock_exchange_fp32_100_steps(model):
+    """Plain FP32 storage and arithmetic: moments within 1e-5 after 100 steps."""
+    kw = dict(C0, model=model)
+    cfg, P = both(pkg.F32, **kw)
+    ref = oracle_trajectory(("c0", model), P, kw, (1, 10, 100, 500))
+    lat = pkg.Lattice(cfg)
+    lat.init_lock_exchange(0.125, 1e-3, 0)
+    lat.step(100)
+    errs = moment_errors(gpu_moments(lat), ref[100][0])
+    print(f"fp32 model {model} errors {errs}", flush=True)
+    assert max(errs.values()) < 1e-5, errs
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_les_trajectory_fp64(model):
+    """LES on (C_s = 0.1) at Re_b = 30000 on a small grid, 60 steps."""
+    kw = dict(nx=96, ny=4, nz=12, model=model, re_b=30000.0, cs_smag=0.1)
+    cfg, P = both(pkg.F64, **kw)
+    ref = _oracle_run(P, kw, (60,))
+    lat = pkg.Lattice(cfg)
+    lat.init_lock_exchange(0.125, 1e-3, 0)
+    lat.step(60)
+    errs = moment_errors(gpu_moments(lat), ref[60][0])
+    assert max(errs.values()) < 1e-10, errs
+
+
+def test_checkpoint_roundtrip_is_bitwise():
+    cfg, P = both(pkg.F32, **dict(C0, cs_smag=0.1))
+    lat = pkg.Lattice(cfg)
+    lat.init_lock_exchange()
+    lat.step(7)
+    slot = lat.checkpoint_save()
+    lat.step(9)
+    a = lat.get_populations()
+    lat.checkpoint_load(slot)
+    assert lat.step_count == 7
+    lat.step(9)
+    b = lat.get_populations()
+    assert lat.step_count == 16
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("storage", [pkg.F64, pkg.F32])
+def test_rest_state_stays_exactly_at_rest(model, storage):
+    """chi = 0: no force, the flow deviations stay exactly zero."""
+    cfg, P = both(storage, nx=70, ny=3, nz=5, model=model, cs_smag=0.1)
+    lat = pkg.Lattice(cfg)
+    lat.init_from_field(torch.zeros(5, 3, 70, dtype=torch.float64, device="cuda"))
+    lat.step(25)
+    f, phi = lat.get_populations()
+    assert np.array_equal(f, np.broadcast_to(P.flow.w.numpy()[:, None, None, None], f.shape))
+    assert not phi.any()
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 4, 1), (1, 1, 5), (2, 1, 3), (4, 2, 65)])
+@pytest.mark.parametrize("model", [0, 1])
+def test_degenerate_and_ragged_grids(shape, model):
+    """Grids of one node in some direction (every neighbour a wall or the node
+    itself) and a ragged x tail: one FP64 step against the oracle."""
+    kw = dict(nx=shape[2], ny=shape[1], nz=shape[0], model=model, re_b=50.0, g_prime=1e-3, cs_smag=0.1)
+    cfg, P = both(pkg.F64, **kw)
+    f, phi = inputs.near_rest_state(P.flow.Q, P.scal.Q, shape, P.flow.w.numpy(), P.scal.w.numpy(), 4, eps=1e-2)
+    lat = pkg.Lattice(cfg)
+    lat.set_populations(f, phi)
+    lat.step(1)
+    f1, phi1 = lat.get_populations()
+    of, ophi = olbm.step(torch.from_numpy(f), torch.from_numpy(phi), P)
+    assert np.abs(f1 - of.numpy()).max() < 1e-13
+    assert np.abs(phi1 - ophi.numpy()).max() < 1e-13
+
+
+def test_set_then_get_is_the_identity():
+    cfg, P = both(pkg.F64, nx=37, ny=3, nz=4, model=0)
+    f, phi = inputs.near_rest_state(27, 7, (4, 3, 37), P.flow.w.numpy(), P.scal.w.numpy(), 9)
+    lat = pkg.Lattice(cfg)
+    lat.set_populations(f, phi)
+    g, p = lat.get_populations()
+    assert np.array_equal(g, f) and np.array_equal(p, phi)
+
+
+def test_error_paths():
+    cfg, P = both(pkg.F32, **C0)
+    lat = pkg.Lattice(cfg)
+    with pytest.raises(pkg.LBMError) as e:
+        lat.step(1)
+    assert e.value.code == pkg.LBM_ESTATE
+    lat.init_lock_exchange()
+    lat.step(0)
+    assert lat.step_count == 0
+    with pytest.raises(pkg.LBMError) as e:
+        lat.step(-1)
+    assert e.value.code == pkg.LBM_EINVAL
+    import ctypes
+    h = ctypes.c_void_p()
+    rc = pkg.lib().lbm_create(ctypes.byref(cfg.c()), ctypes.c_void_p(lat.ws.data_ptr()), 1024, None,
+                              ctypes.byref(h))
+    assert rc == pkg.LBM_ENOMEM
+
+
+def test_nonfinite_state_is_reported():
+    cfg, P = both(pkg.F32, nx=64, ny=2, nz=4, model=0)
+    f, phi = inputs.near_rest_state(27, 7, (4, 2, 64), P.flow.w.numpy(), P.scal.w.numpy(), 2)
+    f[5, 1, 1, 10] = np.nan
+    lat = pkg.Lattice(cfg)
+    lat.set_populations(f, phi)
+    with pytest.raises(pkg.LBMError) as e:
+        lat.diagnostics()
+    assert e.value.code == pkg.LBM_EUNSTABLE
+    d = lat.diagnostics(raise_unstable=False)
+    assert d["nonfinite"] >= 1

@@ -32,11 +32,15 @@ def gpu_moments(lat):
 
 def moment_errors(got, want):
     """Infinity-norm error of each field relative to the oracle field's
-    infinity norm (delta rho = rho - 1 for the density)."""
+    infinity norm: delta rho = rho - 1 for the density, chi, and for every
+    velocity component the velocity magnitude's infinity norm (a component
+    that is itself ~0, e.g. the span velocity of an almost two-dimensional
+    start, would otherwise divide rounding noise by rounding noise)."""
     out = {}
+    umax = np.sqrt(want["ux"] ** 2 + want["uy"] ** 2 + want["uz"] ** 2).max()
     for k in ("rho", "ux", "uy", "uz", "chi"):
         ref = want[k] - 1.0 if k == "rho" else want[k]
-        scale = np.abs(ref).max()
+        scale = umax if k in ("ux", "uy", "uz") else np.abs(ref).max()
         out[k] = float(np.abs(got[k] - want[k]).max() / scale) if scale > 0 else float(np.abs(got[k] - want[k]).max())
     return out
 

@@ -83,6 +83,31 @@ def measure(name, steps, warmup):
             (d["mass"] - d["mass0"]) / d["mass0"], "x_f_nd": d["x_f_nd"]}
 
 
+def stream_copy(nbytes=2 << 30, reps=10):
+    """Device-to-device copy of nbytes with the library's plain streaming copy
+    kernel: the achievable read+write bandwidth on this GPU, and a kernel of
+    known size that scales the HBM byte counters of the profiles."""
+    import torch
+
+    import paper_2112_08479_amd as pkg
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    s_ = torch.cuda.current_stream()
+    pkg.stream_copy(b, a, nbytes, s_)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s_)
+    for _ in range(reps):
+        pkg.stream_copy(b, a, nbytes, s_)
+    e1.record(s_)
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) * 1e-3 / reps
+    assert bool((b[:: 1 << 20] == 1.0).all())
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * nbytes, "GB_per_s": 2 * nbytes / s / 1e9}
+
+
 def traffic_for(name, bpn_launch):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources; else None."""
@@ -139,6 +164,8 @@ def main():
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    copy = stream_copy()
+    print(json.dumps({"progress": "stream_copy", **copy}), file=sys.stderr, flush=True)
     head = measure(args.workload, args.steps, args.warmup)
     print(json.dumps({"progress": "headline", **head}), file=sys.stderr, flush=True)
     variants = []
@@ -174,6 +201,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_for(args.workload, launch_bytes)},
         "cpu_baseline": cpu,
+        "stream_copy_GB_per_s": copy["GB_per_s"],
         "variants": variants,
         "paper_context": {"RAFSINE_D3Q19_BGK_D3Q6_V100_MNUPS": 1307,
                           "VirtualFluids_D3Q27_cumulant_FCM_V100_MNUPS": 1064},

@@ -176,6 +176,13 @@ int lbm_checkpoint_load(lbm_handle* h, const void* dev_slot);
 int lbm_get_populations(lbm_handle* h, double* host_f, double* host_phi);
 int lbm_set_populations(lbm_handle* h, const double* host_f, const double* host_phi);
 
+/* Measurement utility (not part of the method): copies `bytes` (a multiple of
+ * 16) from src_dev to dst_dev with a plain streaming kernel on hip_stream --
+ * the achievable read+write HBM ceiling against which the step kernel's
+ * bandwidth is compared. Asynchronous. LBM_EINVAL on NULL pointers or a size
+ * that is not a multiple of 16. */
+int lbm_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, void* hip_stream);
+
 const char* lbm_last_error(void);
 
 #ifdef __cplusplus

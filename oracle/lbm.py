@@ -129,9 +129,9 @@ def step_at(f, phi, P, nodes):
     restricted to a sample of nodes, for checks at sizes where a full oracle
     step is too slow. Returns (Q, m), (P, m)."""
     nz, ny, nx = f.shape[1:]
-    out_f = torch.empty(P.flow.Q, len(nodes), dtype=torch.float64)
-    out_p = torch.empty(P.scal.Q, len(nodes), dtype=torch.float64)
-    for lat, out, which in ((P.flow, out_f, 0), (P.scal, out_p, 1)):
+    cols = {}
+    plans = ([], [])
+    for which, lat in enumerate((P.flow, P.scal)):
         for m, (k, j, i) in enumerate(nodes):
             for q in range(lat.Q):
                 cx, cy, cz = lat.c_list[q]
@@ -144,7 +144,15 @@ def step_at(f, phi, P, nodes):
                     src, qq = (sk, sj, si), q
                 else:
                     src, qq = (k, j, i), int(lat.opp[q])
-                fs, ps = C.collide(f[:, src[0], src[1], src[2]][:, None],
-                                   phi[:, src[0], src[1], src[2]][:, None], P)
-                out[q, m] = (fs if which == 0 else ps)[qq, 0]
+                col = cols.setdefault(src, len(cols))
+                plans[which].append((q, m, col, qq))
+    ks = torch.tensor([c[0] for c in cols])
+    js = torch.tensor([c[1] for c in cols])
+    iis = torch.tensor([c[2] for c in cols])
+    fs, ps = C.collide(f[:, ks, js, iis], phi[:, ks, js, iis], P)
+    out_f = torch.empty(P.flow.Q, len(nodes), dtype=torch.float64)
+    out_p = torch.empty(P.scal.Q, len(nodes), dtype=torch.float64)
+    for (out, src), plan in zip(((out_f, fs), (out_p, ps)), plans):
+        for q, m, col, qq in plan:
+            out[q, m] = src[qq, col]
     return out_f, out_p

@@ -30,7 +30,7 @@ EXPORTS = [
     "lbm_derive_params", "lbm_workspace_bytes", "lbm_state_bytes", "lbm_create", "lbm_destroy",
     "lbm_init_lock_exchange", "lbm_init_from_field", "lbm_step", "lbm_moments",
     "lbm_diagnostics", "lbm_get_step", "lbm_checkpoint_save", "lbm_checkpoint_load",
-    "lbm_get_populations", "lbm_set_populations", "lbm_last_error",
+    "lbm_get_populations", "lbm_set_populations", "lbm_stream_copy", "lbm_last_error",
 ]
 
 
@@ -90,6 +90,7 @@ def lib():
             "lbm_checkpoint_load": (ctypes.c_int, [vp, vp]),
             "lbm_get_populations": (ctypes.c_int, [vp, vp, vp]),
             "lbm_set_populations": (ctypes.c_int, [vp, vp, vp]),
+            "lbm_stream_copy": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
             "lbm_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -149,6 +150,11 @@ def workspace_bytes(cfg):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def stream_copy(dst, src, nbytes, stream):
+    """Plain streaming copy of nbytes between device tensors (measurement utility)."""
+    check(lib().lbm_stream_copy(_ptr(dst), _ptr(src), int(nbytes), ctypes.c_void_p(stream.cuda_stream)))
 
 
 class Lattice:

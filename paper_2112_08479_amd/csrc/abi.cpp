@@ -128,6 +128,13 @@ extern "C" {
 
 const char* lbm_last_error(void) { return g_err; }
 
+int lbm_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, void* hip_stream) {
+  if (!dst_dev || !src_dev) return fail(LBM_EINVAL, "NULL pointer");
+  if (bytes % 16 != 0) return fail(LBM_EINVAL, "bytes must be a multiple of 16");
+  HIPCHECK(lbm::launch_stream_copy(dst_dev, src_dev, bytes, (hipStream_t)hip_stream));
+  return LBM_OK;
+}
+
 int lbm_derive_params(const lbm_config* cfg, lbm_params* out) {
   if (!out) return fail(LBM_EINVAL, "out is NULL");
   return validate(cfg, out);

@@ -37,9 +37,44 @@ LBM_HD double to_d<double>(double v) { return v; }
 template <>
 LBM_HD double to_d<float>(float v) { return (double)v; }
 
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 1
+#endif
+#ifndef LBM_XCD_REMAP
+#define LBM_XCD_REMAP 0
+#endif
+
+// Post-collision values are not read again before the next launch, so they
+// may bypass the caches on the way to HBM.
 template <typename ST>
 __device__ __forceinline__ void store_val(ST* p, ST v) {
+#if LBM_NT_STORE
+  if constexpr (std::is_same<ST, double>::value || std::is_same<ST, float>::value) {
+    __builtin_nontemporal_store(v, p);
+  } else {
+    uint16_t bits;
+    __builtin_memcpy(&bits, &v, 2);
+    __builtin_nontemporal_store(bits, reinterpret_cast<uint16_t*>(p));
+  }
+#else
   *p = v;
+#endif
+}
+
+// Block order. Consecutive block ids are dealt round-robin to the 8 XCDs
+// (each with its own L2); with the remap every XCD works on a contiguous range
+// of rows, so the partial cache lines shared by neighbouring x-tiles of a row
+// stay within one L2.
+__device__ __forceinline__ int block_order(int b, int nblocks) {
+#if LBM_XCD_REMAP
+  constexpr int kXcd = 8;
+  const int per = nblocks / kXcd;
+  if (b >= per * kXcd) return b;
+  return (b % kXcd) * per + b / kXcd;
+#else
+  (void)nblocks;
+  return b;
+#endif
 }
 
 // ------------------------------------------------------------------- step
@@ -48,29 +83,37 @@ __global__ __launch_bounds__(kBlock) void k_step(const ST* __restrict__ src, ST*
                                                  Grid g, Phys<CT> p, int nbx) {
   using LF = typename ModelT<MODEL>::LF;
   using LS = typename ModelT<MODEL>::LS;
-  const int b = blockIdx.x;
+  constexpr int NPT = kNodesPerThread;
+  const int b = block_order(blockIdx.x, gridDim.x);
   const int row = b / nbx;
-  const int x = (b - row * nbx) * blockDim.x + threadIdx.x;
-  if (x >= g.nx) return;
+  const int x0 = (b - row * nbx) * (int)blockDim.x * NPT;
+  if (x0 + (int)threadIdx.x >= g.nx) return;  // lanes with no node at all
   const int y = row % g.ny, z = row / g.ny;
-  const int64_t node = (int64_t)row * g.nx + x;
-  CT fg[LF::Q], ph[LS::Q];
-  gather<LF, LS, ST, CT>(src, g, x, y, z, node, fg, ph);
-  if constexpr (MODEL == 0) {
-    if constexpr (GEN)
-      collide_cumulant_q27_q7_general<LES, CT>(fg, ph, p);
-    else
-      collide_cumulant_q27_q7<LES, CT>(fg, ph, p);
-  } else {
-    collide_bgk_q19_q6<LES, CT>(fg, ph, p);
+  CT fg[NPT][LF::Q], ph[NPT][LS::Q];
+  gather_rows<LF, LS, NPT, ST, CT>(src, g, x0, y, z, fg, ph);
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    if constexpr (MODEL == 0) {
+      if constexpr (GEN)
+        collide_cumulant_q27_q7_general<LES, CT>(fg[k], ph[k], p);
+      else
+        collide_cumulant_q27_q7<LES, CT>(fg[k], ph[k], p);
+    } else {
+      collide_bgk_q19_q6<LES, CT>(fg[k], ph[k], p);
+    }
   }
-  static_for<0, LF::Q>([&](auto qc) {
-    constexpr int q = decltype(qc)::value;
-    store_val(dst + (int64_t)q * g.n + node, Conv<ST, CT>::store(fg[q]));
-  });
-  static_for<0, LS::Q>([&](auto qc) {
-    constexpr int q = decltype(qc)::value;
-    store_val(dst + (int64_t)(LF::Q + q) * g.n + node, Conv<ST, CT>::store(ph[q]));
+  // block-uniform row pointers + lane index, as for the loads
+  ST* drow = dst + ((int64_t)row * g.nx + x0);
+  const int lane = threadIdx.x;
+  static_for<0, LF::Q + LS::Q>([&](auto qc) {
+    constexpr int a = decltype(qc)::value;
+    ST* pa = drow + (int64_t)a * g.n;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      const int xo = lane + k * (int)blockDim.x;
+      const CT v = a < LF::Q ? fg[k][a < LF::Q ? a : 0] : ph[k][a < LF::Q ? 0 : a - LF::Q];
+      if (k == 0 || x0 + xo < g.nx) store_val(&pa[xo], Conv<ST, CT>::store(v));
+    }
   });
 }
 
@@ -447,8 +490,10 @@ static bool general_rates(const lbm_handle* h) {
 
 hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
   const Grid g = grid_of(h);
-  const int bx = block_x(h);
-  const int nbx = (g.nx + bx - 1) / bx;
+  constexpr int NPT = kNodesPerThread;
+  const int per_thread_x = (g.nx + NPT - 1) / NPT;  // x-extent in threads if one block
+  const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
+  const int nbx = (g.nx + bx * NPT - 1) / (bx * NPT);
   const unsigned blocks = (unsigned)((int64_t)nbx * g.ny * g.nz);
   const bool les = h->cfg.cs_smag > 0.0;
   const bool gen = general_rates(h);
@@ -576,6 +621,29 @@ hipError_t launch_set_pop(lbm_handle* h, int a, const double* src) {
       return hipGetLastError();
     });
   });
+}
+
+// STREAM-style copy: 16-byte loads, non-temporal 16-byte stores, grid-stride.
+__global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ src,
+                                                     uint4* __restrict__ dst, int64_t n16) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
+    const uint4 v = src[i];
+    __builtin_nontemporal_store(v.x, &dst[i].x);
+    __builtin_nontemporal_store(v.y, &dst[i].y);
+    __builtin_nontemporal_store(v.z, &dst[i].z);
+    __builtin_nontemporal_store(v.w, &dst[i].w);
+  }
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  int64_t blocks = (n16 + 255) / 256;
+  if (blocks > 256 * 64) blocks = 256 * 64;  // 64 blocks per CU, grid-stride beyond
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, stream,
+                     static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+  return hipGetLastError();
 }
 
 hipError_t launch_copy_state(lbm_handle* h, const void* src, void* dst) {

@@ -134,9 +134,15 @@ struct Grid {
 // node (x, y, z) pulls from: the neighbour x - c_q when it is a fluid node
 // (y taken modulo ny), else -- half-way bounce-back -- population opp(q) of
 // the node itself.
-template <class L, int q>
-LBM_HD int64_t pull_offset(const Grid& g, int base, int x, int y, int z, int64_t node) {
+// The array base pointers depend only on q and the launch (scalar registers);
+// node indices fit in 32 bits (n < 2^31), computed unsigned so that the
+// unselected out-of-range candidate at a wall is harmless.
+template <class L, int q, typename ST>
+LBM_HD const ST* pull_ptr(const ST* __restrict__ src, const Grid& g, int base, int x, int y, int z,
+                          uint32_t node) {
   constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
+  const ST* pq = src + (int64_t)(base + q) * g.n;
+  const ST* po = src + (int64_t)(base + opp<L>(q)) * g.n;
   const int xs = x - cx;
   const int zs = z - cz;
   int ys = y - cy;
@@ -145,8 +151,92 @@ LBM_HD int64_t pull_offset(const Grid& g, int base, int x, int y, int z, int64_t
   bool wall = false;
   if (cx != 0) wall = wall || ((unsigned)xs >= (unsigned)g.nx);
   if (cz != 0) wall = wall || ((unsigned)zs >= (unsigned)g.nz);
-  const int64_t src = ((int64_t)zs * g.ny + ys) * g.nx + xs;
-  return wall ? (int64_t)(base + opp<L>(q)) * g.n + node : (int64_t)(base + q) * g.n + src;
+  const uint32_t s = ((uint32_t)zs * (uint32_t)g.ny + (uint32_t)ys) * (uint32_t)g.nx + (uint32_t)xs;
+  return wall ? po + node : pq + s;
+}
+
+template <int I, int N, class F>
+LBM_HD void static_for(F&& f);
+
+// Gather for a thread block that covers NPT * blockDim.x consecutive nodes
+// x0 .. of one row (y, z); thread `lane` handles x0 + lane + k blockDim.x,
+// k < NPT. Every pull address is a block-uniform row pointer (scalar
+// registers, advanced by one array per population) plus the lane index, so
+// the gather costs no per-lane address arithmetic:
+//   - y is periodic: the source row is chosen per block;
+//   - a source beyond a z wall (uniform per block) selects the bounce-back
+//     pointer, the node's own opposite population;
+//   - lanes at an x wall first load a neighbouring element of the buffer
+//     (never used) and, in the waves that hold such a lane only, take the
+//     bounce-back value afterwards. That first load stays inside the buffer
+//     because its first array is a rest population (no x shift reads below
+//     it) and its last array has c_x = 0 (nothing reads past its end) --
+//     checked by the static_asserts. Lane offsets are clamped to the row so
+//     that tail lanes of a ragged row never read past it.
+template <class L, int base, int NPT, typename ST, typename CT>
+__device__ __forceinline__ void pull_lattice(const ST* __restrict__ src, const Grid& g,
+                                             int64_t row0, int y, int z, const unsigned* li,
+                                             bool wave_at_wall, const int* xk,
+                                             CT (&out)[NPT][L::Q]) {
+  const int dy_m = (y == g.ny - 1) ? -(g.ny - 1) : 1;  // c_y = -1: source row y + 1
+  const int dy_p = (y == 0) ? g.ny - 1 : -1;           // c_y = +1: source row y - 1
+  const ST* arr0 = src + (int64_t)base * g.n + row0;
+  {
+    const ST* arr = arr0;
+    static_for<0, L::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
+      constexpr int o = opp<L>(q);
+      const bool zwall = cz != 0 && (unsigned)(z - cz) >= (unsigned)g.nz;
+      const int dy = cy == 0 ? 0 : (cy == 1 ? dy_p : dy_m);
+      const int64_t sh = zwall ? (int64_t)(o - q) * g.n : ((int64_t)(-cz) * g.ny + dy) * g.nx - cx;
+      const ST* p = arr + sh;
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) out[k][q] = Conv<ST, CT>::load(p[li[k]]);
+      arr += g.n;
+    });
+  }
+  if (wave_at_wall) {  // wave-uniform: this wave holds x = 0 or x = nx - 1
+    const ST* arr = arr0;
+    static_for<0, L::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr int cx = L::cx[q], cz = L::cz[q];
+      constexpr int o = opp<L>(q);
+      if constexpr (cx != 0) {
+        const bool zwall = cz != 0 && (unsigned)(z - cz) >= (unsigned)g.nz;
+        const ST* po = arr + (int64_t)(o - q) * g.n;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+          const bool wall = !zwall && (unsigned)(xk[k] - cx) >= (unsigned)g.nx;
+          const CT b = Conv<ST, CT>::load(po[li[k]]);
+          out[k][q] = wall ? b : out[k][q];
+        }
+      }
+      arr += g.n;
+    });
+  }
+}
+
+template <class LF, class LS, int NPT, typename ST, typename CT>
+__device__ __forceinline__ void gather_rows(const ST* __restrict__ src, const Grid& g, int x0, int y,
+                                            int z, CT (&fg)[NPT][LF::Q], CT (&ph)[NPT][LS::Q]) {
+  static_assert(LF::cx[0] == 0 && LF::cy[0] == 0 && LF::cz[0] == 0, "buffer must start at rest");
+  static_assert(LS::cx[LS::Q - 1] == 0, "last array must not be x-shifted");
+  const int64_t row0 = ((int64_t)z * g.ny + y) * g.nx + x0;
+  unsigned li[NPT];
+  int xk[NPT];
+  const unsigned last = (unsigned)(g.nx - 1 - x0);  // >= 0: the block holds a node
+  bool at_wall = false;
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const unsigned o = threadIdx.x + (unsigned)k * blockDim.x;
+    li[k] = o < last ? o : last;
+    xk[k] = x0 + (int)o;
+    at_wall = at_wall || xk[k] == 0 || xk[k] == g.nx - 1;
+  }
+  const bool wave_at_wall = __builtin_amdgcn_ballot_w64(at_wall) != 0;
+  pull_lattice<LF, 0, NPT, ST, CT>(src, g, row0, y, z, li, wave_at_wall, xk, fg);
+  pull_lattice<LS, LF::Q, NPT, ST, CT>(src, g, row0, y, z, li, wave_at_wall, xk, ph);
 }
 
 template <int I, int N, class F>
@@ -164,11 +254,11 @@ LBM_HD void gather(const ST* __restrict__ src, const Grid& g, int x, int y, int 
                    CT* fg, CT* ph) {
   static_for<0, LF::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    fg[q] = Conv<ST, CT>::load(src[pull_offset<LF, q>(g, 0, x, y, z, node)]);
+    fg[q] = Conv<ST, CT>::load(*pull_ptr<LF, q>(src, g, 0, x, y, z, (uint32_t)node));
   });
   static_for<0, LS::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    ph[q] = Conv<ST, CT>::load(src[pull_offset<LS, q>(g, LF::Q, x, y, z, node)]);
+    ph[q] = Conv<ST, CT>::load(*pull_ptr<LS, q>(src, g, LF::Q, x, y, z, (uint32_t)node));
   });
 }
 

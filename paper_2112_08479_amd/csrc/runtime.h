@@ -34,7 +34,14 @@ struct lbm_handle {
 
 namespace lbm {
 
-constexpr int kBlock = 256;
+#ifndef LBM_BLOCK
+#define LBM_BLOCK 256
+#endif
+constexpr int kBlock = LBM_BLOCK;  // threads per block along x (multiple of 64)
+#ifndef LBM_NPT
+#define LBM_NPT 2
+#endif
+constexpr int kNodesPerThread = LBM_NPT;  // step kernel: nodes per thread along x
 constexpr int kDiagSlots = 8;  // partial sums per diagnostic block
 
 // kernels.hip
@@ -47,5 +54,6 @@ hipError_t launch_diag(lbm_handle* h, double* out);
 hipError_t launch_get_pop(lbm_handle* h, int q, double* dst);
 hipError_t launch_set_pop(lbm_handle* h, int q, const double* src);
 hipError_t launch_copy_state(lbm_handle* h, const void* src, void* dst);
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
 }  // namespace lbm

@@ -195,3 +195,18 @@ def test_span_symmetry_without_noise(model):
     for j in range(1, 3):
         assert torch.equal(f[:, :, j], f[:, :, 0])
         assert torch.equal(phi[:, :, j], phi[:, :, 0])
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_sampled_step_equals_full_step(model):
+    cfg = Config(20, 3, 6, model=model, re_b=500.0, cs_smag=0.1)
+    P = derive(cfg)
+    f, phi = lbm.init_state(P, lbm.chi0_lock_exchange(cfg, seed=2))
+    for _ in range(3):
+        f, phi = lbm.step(f, phi, P)
+    f1, p1 = lbm.step(f, phi, P)
+    nodes = [(0, 0, 0), (5, 2, 19), (2, 1, 2), (3, 0, 10), (0, 2, 19), (5, 0, 0)]
+    sf, sp = lbm.step_at(f, phi, P, nodes)
+    for m, (k, j, i) in enumerate(nodes):       # batch size changes BLAS summation order
+        assert torch.allclose(sf[:, m], f1[:, k, j, i], rtol=0, atol=1e-15)
+        assert torch.allclose(sp[:, m], p1[:, k, j, i], rtol=0, atol=1e-15)

@@ -176,6 +176,27 @@ int lbm_checkpoint_load(lbm_handle* h, const void* dev_slot);
 int lbm_get_populations(lbm_handle* h, double* host_f, double* host_phi);
 int lbm_set_populations(lbm_handle* h, const double* host_f, const double* host_phi);
 
+/* ------------------------------------------------------------------------
+ * Differentiation form. J = w_front x_f(n) + w_fw (1/n) sum_{m=1..n} F_w(m)
+ * (lattice units; x_f and F_w as in lbm_diag: front of Sec. 3.1, wall
+ * friction of Eq. 62, 64) for an n-step run started from the current state,
+ * which must be a fresh initialisation (step 0). The forward pass keeps a
+ * checkpoint every k_ckpt steps; the reverse pass recomputes each segment and
+ * runs the hand-written adjoint of the gather with bounce-back and of the
+ * local collision (Eq. 17, 21-35, 54-58). Outputs: *J_out, *dJ_dcs (C_s),
+ * *dJ_dsct (Sc_T) as host doubles and dJ/dchi0 (nx*ny*nz doubles, device;
+ * chi0 enters through phi(0) = w_phi chi0). Non-smooth points: zero
+ * subgradient of sqrt(Q) at Q = 0; the front uses the active column i* and
+ * the first depth maximum. Requires omega3..omega6 = 1 for the cumulant model
+ * and storage LBM_F32 or LBM_F64 (LBM_EINVAL otherwise); LBM_ESTATE if the
+ * handle is not at step 0. adj_ws: device scratch of
+ * lbm_adjoint_workspace_bytes(cfg, n, k_ckpt) bytes (LBM_ENOMEM if smaller).
+ * Leaves the handle at step n. Synchronises. */
+size_t lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t n_steps, int64_t k_ckpt);
+int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_front,
+                    double w_fw, void* adj_ws, size_t adj_bytes, double* J_out,
+                    double* dJ_dcs, double* dJ_dsct, double* dJ_dchi0_dev);
+
 /* Measurement utility (not part of the method): copies `bytes` (a multiple of
  * 16) from src_dev to dst_dev with a plain streaming kernel on hip_stream --
  * the achievable read+write HBM ceiling against which the step kernel's

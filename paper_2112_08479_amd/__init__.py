@@ -30,7 +30,8 @@ EXPORTS = [
     "lbm_derive_params", "lbm_workspace_bytes", "lbm_state_bytes", "lbm_create", "lbm_destroy",
     "lbm_init_lock_exchange", "lbm_init_from_field", "lbm_step", "lbm_moments",
     "lbm_diagnostics", "lbm_get_step", "lbm_checkpoint_save", "lbm_checkpoint_load",
-    "lbm_get_populations", "lbm_set_populations", "lbm_stream_copy", "lbm_last_error",
+    "lbm_get_populations", "lbm_set_populations", "lbm_adjoint_workspace_bytes",
+    "lbm_adjoint_run", "lbm_stream_copy", "lbm_last_error",
 ]
 
 
@@ -91,6 +92,10 @@ def lib():
             "lbm_get_populations": (ctypes.c_int, [vp, vp, vp]),
             "lbm_set_populations": (ctypes.c_int, [vp, vp, vp]),
             "lbm_stream_copy": (ctypes.c_int, [vp, vp, ctypes.c_size_t, vp]),
+            "lbm_adjoint_workspace_bytes": (ctypes.c_size_t, [cfgp, i64, i64]),
+            "lbm_adjoint_run": (ctypes.c_int, [vp, i64, i64, dbl, dbl, vp, ctypes.c_size_t,
+                                               ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                               ctypes.POINTER(dbl), vp]),
             "lbm_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -266,3 +271,54 @@ class Lattice:
                                      _ptr(ws), nb, ctypes.byref(J), ctypes.byref(dcs),
                                      ctypes.byref(dsct), _ptr(gchi)))
         return J.value, dcs.value, dsct.value, gchi
+
+
+def lock_exchange_objective(chi0, cs_smag, sc_t, cfg, n_steps, k_ckpt=100, w_front=1.0, w_fw=1.0,
+                            lock_fraction=0.125):
+    """J = w_front x_f(n) + w_fw (1/n) sum_{m=1..n} F_w(m) of an n-step run from
+    the initial concentration chi0 (float64 tensor (nz, ny, nx) on the GPU),
+    differentiable with respect to chi0, cs_smag and sc_t (0-d tensors)
+    through the library's hand-written adjoint (checkpoint every k_ckpt
+    steps). cfg gives the grid, model, storage and the other parameters."""
+    return _Objective.apply(chi0, cs_smag, sc_t, cfg, int(n_steps), int(k_ckpt), float(w_front),
+                            float(w_fw), float(lock_fraction))
+
+
+def _objective_cls():
+    import dataclasses
+
+    import torch
+
+    class Objective(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, chi0, cs, sct, cfg, n_steps, k_ckpt, w_front, w_fw, lock_fraction):
+            c = dataclasses.replace(cfg, cs_smag=float(cs), sc_t=float(sct))
+            lat = Lattice(c, device=chi0.device)
+            lat.init_from_field(chi0.detach().to(torch.float64).contiguous(), lock_fraction)
+            J, dcs, dsct, gchi = lat.adjoint_run(n_steps, k_ckpt, w_front, w_fw)
+            lat.close()
+            ctx.save_for_backward(gchi.to(chi0.dtype), torch.tensor(dcs, dtype=cs.dtype),
+                                  torch.tensor(dsct, dtype=sct.dtype))
+            return torch.tensor(J, dtype=torch.float64, device=chi0.device)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            gchi, dcs, dsct = ctx.saved_tensors
+            g = gJ.to(gchi.device)
+            return (g * gchi, (g.cpu() * dcs).to(dcs.dtype), (g.cpu() * dsct).to(dsct.dtype),
+                    None, None, None, None, None, None)
+
+    return Objective
+
+
+class _Lazy:
+    _cls = None
+
+    @classmethod
+    def apply(cls, *a):
+        if cls._cls is None:
+            cls._cls = _objective_cls()
+        return cls._cls.apply(*a)
+
+
+_Objective = _Lazy

@@ -7,7 +7,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <utility>
 
 #include "runtime.h"
 
@@ -127,6 +129,127 @@ int run_diag(lbm_handle* h, double* dst) {
 extern "C" {
 
 const char* lbm_last_error(void) { return g_err; }
+
+// ------------------------------------------------------------ adjoint
+namespace {
+struct AdjLayout {
+  size_t buf, ckpt, traj, lam, gpart, fwpart, small, total;
+  int64_t nseg, ktraj;
+};
+
+AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, int64_t k) {
+  AdjLayout L;
+  const int64_t n = (int64_t)c->nx * c->ny * c->nz;
+  const int qt = p->q_flow + p->q_scalar;
+  L.buf = align256((size_t)qt * n * storage_bytes(c->storage));
+  L.nseg = (n_steps + k - 1) / k;
+  L.ktraj = k < n_steps ? k : n_steps;
+  const int bx = block_x(c->nx);
+  const int64_t ablocks = (int64_t)((c->nx + bx - 1) / bx) * c->ny * c->nz;
+  const int64_t fblocks = ((int64_t)c->nx * c->ny + lbm::kBlock - 1) / lbm::kBlock;
+  size_t off = 0;
+  L.ckpt = off;
+  off += (size_t)L.nseg * L.buf;
+  L.traj = off;
+  off += (size_t)L.ktraj * L.buf;
+  L.lam = off;
+  off += 2 * L.buf;
+  L.gpart = off;
+  off += align256((size_t)ablocks * 2 * sizeof(double));
+  L.fwpart = off;
+  off += align256((size_t)fblocks * 2 * sizeof(double));
+  L.small = off;
+  off += 256;
+  L.total = off;
+  return L;
+}
+
+int adjoint_supported(const lbm_config* c) {
+  if (c->storage != LBM_F32 && c->storage != LBM_F64)
+    return fail(LBM_EINVAL, "the adjoint needs LBM_F32 or LBM_F64 storage");
+  if (c->model == LBM_CUMULANT27_Q7 &&
+      (c->omega3 != 1.0 || c->omega4 != 1.0 || c->omega5 != 1.0 || c->omega6 != 1.0))
+    return fail(LBM_EINVAL, "the cumulant adjoint needs omega3..omega6 = 1");
+  return LBM_OK;
+}
+}  // namespace
+
+size_t lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t n_steps, int64_t k_ckpt) {
+  lbm_params p;
+  if (validate(cfg, &p) != LBM_OK || n_steps < 1 || k_ckpt < 1) return 0;
+  if (adjoint_supported(cfg) != LBM_OK) return 0;
+  return adj_layout(cfg, &p, n_steps, k_ckpt).total;
+}
+
+int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_front, double w_fw,
+                    void* adj_ws, size_t adj_bytes, double* J_out, double* dJ_dcs,
+                    double* dJ_dsct, double* dJ_dchi0_dev) {
+  int rc = require_ready(h);
+  if (rc) return rc;
+  if (h->step != 0) return fail(LBM_ESTATE, "the adjoint run must start from step 0 (step is %lld)",
+                                (long long)h->step);
+  if (n_steps < 1 || k_ckpt < 1) return fail(LBM_EINVAL, "n_steps and k_ckpt must be >= 1");
+  if (!adj_ws || !J_out || !dJ_dcs || !dJ_dsct || !dJ_dchi0_dev) return fail(LBM_EINVAL, "NULL argument");
+  if (((uintptr_t)adj_ws & 255) != 0) return fail(LBM_EINVAL, "adjoint workspace not 256-byte aligned");
+  rc = adjoint_supported(&h->cfg);
+  if (rc) return rc;
+  const AdjLayout L = adj_layout(&h->cfg, &h->prm, n_steps, k_ckpt);
+  if (adj_bytes < L.total)
+    return fail(LBM_ENOMEM, "adjoint workspace of %zu bytes, %zu needed", adj_bytes, L.total);
+  rc = set_device(h);
+  if (rc) return rc;
+  char* ws = (char*)adj_ws;
+  double* gpart = (double*)(ws + L.gpart);
+  double* fwpart = (double*)(ws + L.fwpart);
+  double* small = (double*)(ws + L.small);  // [0] F_w sum, [8..12] front seed, [16..17] params
+  const int nblk = lbm::adjoint_blocks(h);
+  const size_t sbytes = (size_t)h->qt * h->n * h->esize;
+  auto ckpt = [&](int64_t s) { return (void*)(ws + L.ckpt + (size_t)s * L.buf); };
+  auto traj = [&](int64_t i) { return (void*)(ws + L.traj + (size_t)i * L.buf); };
+  HIPCHECK(lbm::launch_zero(h, gpart, 2 * (int64_t)nblk));
+  HIPCHECK(lbm::launch_zero(h, small, 32));
+  // forward with checkpoints; F_w(m) accumulated for m = 1..n
+  for (int64_t s = 0; s < L.nseg; ++s) {
+    HIPCHECK(hipMemcpyAsync(ckpt(s), h->buf[h->cur], sbytes, hipMemcpyDeviceToDevice, h->stream));
+    const int64_t steps = std::min<int64_t>(k_ckpt, n_steps - s * k_ckpt);
+    for (int64_t i = 0; i < steps; ++i) {
+      HIPCHECK(lbm::launch_step(h, h->buf[h->cur], h->buf[h->cur ^ 1]));
+      h->cur ^= 1;
+      h->step += 1;
+      HIPCHECK(lbm::launch_fw_accumulate(h, h->buf[h->cur], fwpart, small));
+    }
+  }
+  // final state: front and its seed, lambda(n)
+  HIPCHECK(lbm::launch_diag(h, h->dres));
+  HIPCHECK(lbm::launch_front_seed(h, w_front, small + 8));
+  const double a0 = h->cfg.nz >= 2 ? w_fw / (double)n_steps * h->prm.nu0 * 3.0 : 0.0;
+  const double a1 = h->cfg.nz >= 2 ? -w_fw / (double)n_steps * h->prm.nu0 / 3.0 : 0.0;
+  void* lam_next = ws + L.lam;
+  void* lam_out = ws + L.lam + L.buf;
+  HIPCHECK(lbm::launch_adjoint_seed(h, h->buf[h->cur], lam_next, a0, a1, small + 8));
+  // reverse sweep over the segments, recomputing each from its checkpoint
+  for (int64_t s = L.nseg - 1; s >= 0; --s) {
+    const int64_t m0 = s * k_ckpt;
+    const int64_t e = std::min<int64_t>(m0 + k_ckpt, n_steps);
+    HIPCHECK(hipMemcpyAsync(traj(0), ckpt(s), sbytes, hipMemcpyDeviceToDevice, h->stream));
+    for (int64_t i = 0; i + 1 < e - m0; ++i) HIPCHECK(lbm::launch_step(h, traj(i), traj(i + 1)));
+    for (int64_t m = e - 1; m >= m0; --m) {
+      const bool seed = m >= 1;
+      HIPCHECK(lbm::launch_adjoint_step(h, traj(m - m0), lam_next, lam_out, seed ? a0 : 0.0,
+                                        seed ? a1 : 0.0, gpart, m == 0 ? dJ_dchi0_dev : nullptr));
+      std::swap(lam_next, lam_out);
+    }
+  }
+  HIPCHECK(lbm::launch_sum_pairs(h, gpart, nblk, small + 16));
+  double hs[32], r[8];
+  HIPCHECK(hipMemcpyAsync(hs, small, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipMemcpyAsync(r, h->dres, sizeof(r), hipMemcpyDeviceToHost, h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  *J_out = w_front * (r[3] - h->x0) + w_fw * hs[0] / (double)n_steps;
+  *dJ_dcs = hs[16];
+  *dJ_dsct = hs[17];
+  return LBM_OK;
+}
 
 int lbm_stream_copy(void* dst_dev, const void* src_dev, size_t bytes, void* hip_stream) {
   if (!dst_dev || !src_dev) return fail(LBM_EINVAL, "NULL pointer");

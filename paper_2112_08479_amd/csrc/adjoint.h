@@ -1,0 +1,372 @@
+// Reverse-mode derivative (vector-Jacobian product) of the local collisions
+// in collide.h, written out by hand: given the pre-collision deviations g,
+// scalar populations ph and the adjoints mg, mp of the post-collision values,
+// return the adjoints gb, pb of the inputs and accumulate the adjoints of the
+// parameters c_les = 18 sqrt(2) C_s^2 and inv_sct = 1 / Sc_T.
+//
+// Each function first recomputes the forward quantities it needs, in the
+// order of the forward code, then runs the chain rule backwards through them.
+// The cumulant version covers omega3..omega6 = 1 (every cumulant above
+// second order reset to 0). Non-smooth points: sqrt(Q) at Q = 0 takes the
+// zero subgradient.
+#pragma once
+
+#include "collide.h"
+
+namespace lbm {
+
+// adjoint of inv1d
+template <typename CT>
+LBM_HD void inv1d_vjp(CT o0, CT o1, CT o2, CT u, CT K, CT btm, CT bt0, CT btp, CT& bo0, CT& bo1,
+                      CT& bo2, CT& bu) {
+  const CT A = K + o0, uu = u * u;
+  bo0 = bt0 * (CT(1) - uu) + CT(0.5) * (btp * (uu + u) + btm * (uu - u));
+  bo1 = -CT(2) * u * bt0 + CT(0.5) * (btp * (CT(1) + CT(2) * u) + btm * (CT(2) * u - CT(1)));
+  bo2 = -bt0 + CT(0.5) * (btp + btm);
+  bu += bt0 * (-CT(2) * o1 - CT(2) * u * A) + CT(0.5) * btp * (CT(2) * o1 + (CT(2) * u + CT(1)) * A) +
+        CT(0.5) * btm * (CT(2) * o1 + (CT(2) * u - CT(1)) * A);
+}
+
+// adjoint of inverse_chimera: gb (population order) -> mb[9a+3b+c] and the
+// adjoints of the three velocity components
+template <typename CT>
+LBM_HD void inverse_chimera_vjp(const CT* m, CT ux, CT uy, CT uz, const CT* gbar, CT* mb, CT& bux,
+                                CT& buy, CT& buz) {
+  CT B[27], A[27], Ab[27], Bb[27];
+  static_for<0, 9>([&](auto ic) {  // forward x pass
+    constexpr int i = decltype(ic)::value, b = i / 3, c = i % 3;
+    constexpr double K = k1d(b) * k1d(c);
+    inv1d<CT>(m[b * 3 + c], m[9 + b * 3 + c], m[18 + b * 3 + c], ux, CT(K), B[b * 3 + c],
+              B[9 + b * 3 + c], B[18 + b * 3 + c]);
+  });
+  static_for<0, 9>([&](auto ic) {  // forward y pass
+    constexpr int i = decltype(ic)::value, cxi = i / 3, c = i % 3;
+    constexpr double K = w1d(cxi) * k1d(c);
+    inv1d<CT>(B[cxi * 9 + c], B[cxi * 9 + 3 + c], B[cxi * 9 + 6 + c], uy, CT(K), A[cxi * 9 + c],
+              A[cxi * 9 + 3 + c], A[cxi * 9 + 6 + c]);
+  });
+  static_for<0, 9>([&](auto ic) {  // reverse z pass
+    constexpr int i = decltype(ic)::value, cxi = i / 3, cyi = i % 3;
+    constexpr double K = w1d(cxi) * w1d(cyi);
+    const int o = cxi * 9 + cyi * 3;
+    inv1d_vjp<CT>(A[o], A[o + 1], A[o + 2], uz, CT(K), gbar[idx27(cxi - 1, cyi - 1, -1)],
+                  gbar[idx27(cxi - 1, cyi - 1, 0)], gbar[idx27(cxi - 1, cyi - 1, 1)], Ab[o], Ab[o + 1],
+                  Ab[o + 2], buz);
+  });
+  static_for<0, 9>([&](auto ic) {  // reverse y pass
+    constexpr int i = decltype(ic)::value, cxi = i / 3, c = i % 3;
+    constexpr double K = w1d(cxi) * k1d(c);
+    const int o = cxi * 9 + c;
+    inv1d_vjp<CT>(B[o], B[o + 3], B[o + 6], uy, CT(K), Ab[o], Ab[o + 3], Ab[o + 6], Bb[o], Bb[o + 3],
+                  Bb[o + 6], buy);
+  });
+  static_for<0, 9>([&](auto ic) {  // reverse x pass
+    constexpr int i = decltype(ic)::value, b = i / 3, c = i % 3;
+    constexpr double K = k1d(b) * k1d(c);
+    const int o = b * 3 + c;
+    inv1d_vjp<CT>(m[o], m[9 + o], m[18 + o], ux, CT(K), Bb[o], Bb[9 + o], Bb[18 + o], mb[o],
+                  mb[9 + o], mb[18 + o], bux);
+  });
+}
+
+// adjoint of collide_scalar. Inputs: forward values; mp = adjoint of phi*.
+// Outputs: pb (set), and accumulates bchi, bu*, btau and b_isct.
+template <class LS, bool LES, typename CT>
+LBM_HD void scalar_vjp(const CT* ph, CT chi, CT ux, CT uy, CT uz, CT tau, const Phys<CT>& p,
+                       const CT* mp, CT* pb, CT& bchi, CT& bux, CT& buy, CT& buz, CT& btau,
+                       CT& b_isct) {
+  CT tau_phi = p.tau_phi0;
+  if constexpr (LES) {
+    const CT nu_t = (tau - p.tau0) * CT(1.0 / 3.0);
+    tau_phi = CT(0.5) + (p.d0 + nu_t * p.inv_sct) * p.inv_cs2phi;
+  }
+  const CT wphi = CT(1) / tau_phi;
+  CT bwphi = CT(0);
+  static_for<0, LS::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int cx = LS::cx[q], cy = LS::cy[q], cz = LS::cz[q];
+    constexpr double W = weight<LS>(q);
+    CT cu = CT(0);
+    if (cx) cu += CT(cx) * ux;
+    if (cy) cu += CT(cy) * uy;
+    if (cz) cu += CT(cz) * uz;
+    const CT e = CT(W) * (CT(1) + cu * p.inv_cs2phi);
+    pb[q] = (CT(1) - wphi) * mp[q];
+    bwphi += mp[q] * (e * chi - ph[q]);
+    bchi += mp[q] * wphi * e;
+    const CT t = mp[q] * wphi * CT(W) * chi * p.inv_cs2phi;
+    if (cx) bux += CT(cx) * t;
+    if (cy) buy += CT(cy) * t;
+    if (cz) buz += CT(cz) * t;
+  });
+  if constexpr (LES) {
+    const CT btp = -bwphi / (tau_phi * tau_phi);
+    btau += btp * p.inv_cs2phi * p.inv_sct * CT(1.0 / 3.0);
+    b_isct += btp * p.inv_cs2phi * (tau - p.tau0) * CT(1.0 / 3.0);
+  }
+}
+
+template <class L, typename CT>
+LBM_HD void flow_moments_vjp(CT bdrho, CT bjx, CT bjy, CT bjz, CT bpxx, CT bpyy, CT bpzz, CT bpxy,
+                             CT bpxz, CT bpyz, CT* gb) {
+  static_for<0, L::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
+    CT v = bdrho;
+    if (cx) v += CT(cx) * bjx + bpxx;
+    if (cy) v += CT(cy) * bjy + bpyy;
+    if (cz) v += CT(cz) * bjz + bpzz;
+    if (cx * cy) v += CT(cx * cy) * bpxy;
+    if (cx * cz) v += CT(cx * cz) * bpxz;
+    if (cy * cz) v += CT(cy * cz) * bpyz;
+    gb[q] += v;
+  });
+}
+
+// ---- cumulant D3Q27 + D3Q7, omega3..omega6 = 1
+template <bool LES, typename CT>
+LBM_HD void vjp_cumulant_q27_q7(const CT* g, const CT* ph, const CT* mg, const CT* mp,
+                                const Phys<CT>& p, CT* gb, CT* pb, CT& b_cles, CT& b_isct) {
+  // ---- forward recompute
+  CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
+  flow_moments<Q27>(g, drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz);
+  const CT chi = scalar_sum<Q7>(ph);
+  const CT rho = CT(1) + drho;
+  const CT ir = CT(1) / rho;
+  const CT Fz = -p.g * chi;
+  const CT ux = jx * ir, uy = jy * ir, uz = jz * ir;
+  const CT third = CT(1.0 / 3.0), ninth = CT(1.0 / 9.0);
+  const CT dxx = (pxx - drho * third) * ir - ux * ux;
+  const CT dyy = (pyy - drho * third) * ir - uy * uy;
+  const CT dzz = (pzz - drho * third) * ir - uz * uz;
+  const CT dxy = pxy * ir - ux * uy;
+  const CT dxz = pxz * ir - ux * uz;
+  const CT dyz = pyz * ir - uy * uz;
+  CT tau = p.tau0, s = CT(0), R = CT(0);
+  if constexpr (LES) {
+    const CT q2 = dxx * dxx + dyy * dyy + dzz * dzz + CT(2) * (dxy * dxy + dxz * dxz + dyz * dyz);
+    s = sqrt(q2);
+    R = sqrt(p.tau0 * p.tau0 + p.c_les * s);
+    tau = CT(0.5) * (p.tau0 + R);
+  }
+  const CT a1 = CT(1) - CT(1) / tau;
+  CT exx = dxx, eyy = dyy, ezz = dzz, exy = dxy, exz = dxz, eyz = dyz;
+  relax_second(a1, p.omega2, exx, eyy, ezz, exy, exz, eyz);
+  const CT T3 = (dxx + dyy + dzz) * third;
+  const CT vz = (jz + Fz) * ir;
+  CT m[27];
+  static_for<0, 27>([&](auto ic) { m[decltype(ic)::value] = CT(0); });
+  const CT W24 = (exx + eyy) * third + exx * eyy + CT(2) * exy * exy;
+  const CT W20 = (exx + ezz) * third + exx * ezz + CT(2) * exz * exz;
+  const CT W8 = (eyy + ezz) * third + eyy * ezz + CT(2) * eyz * eyz;
+  const CT W22 = (third + exx) * eyz + CT(2) * exy * exz;
+  const CT W16 = (third + eyy) * exz + CT(2) * exy * eyz;
+  const CT W14 = (third + ezz) * exy + CT(2) * exz * eyz;
+  const CT W26 = (exx + eyy + ezz) * ninth + (exx * eyy + exx * ezz + eyy * ezz) * third +
+                 exx * eyy * ezz +
+                 CT(2) * ((third + exx) * eyz * eyz + (third + eyy) * exz * exz +
+                          (third + ezz) * exy * exy) +
+                 CT(8) * exy * exz * eyz;
+  m[0] = drho;
+  m[18] = rho * exx + drho * third;
+  m[6] = rho * eyy + drho * third;
+  m[2] = rho * ezz + drho * third;
+  m[12] = rho * exy;
+  m[10] = rho * exz;
+  m[4] = rho * eyz;
+  m[24] = rho * W24 + drho * ninth;
+  m[20] = rho * W20 + drho * ninth;
+  m[8] = rho * W8 + drho * ninth;
+  m[22] = rho * W22;
+  m[16] = rho * W16;
+  m[14] = rho * W14;
+  m[26] = rho * W26 + drho * CT(1.0 / 27.0);
+  const CT uzs = (jz + CT(0.5) * Fz) * ir;  // scalar velocity (Eq. 20)
+
+  // ---- reverse
+  CT bchi = CT(0), bux = CT(0), buy = CT(0), buz = CT(0), btau = CT(0);
+  CT buzs = CT(0);
+  scalar_vjp<Q7, LES, CT>(ph, chi, ux, uy, uzs, tau, p, mp, pb, bchi, bux, buy, buzs, btau, b_isct);
+  CT mb[27];
+  CT bvz = CT(0);
+  inverse_chimera_vjp<CT>(m, ux, uy, vz, mg, mb, bux, buy, bvz);
+  CT brho = CT(0), bdrho = CT(0);
+  CT bexx = CT(0), beyy = CT(0), bezz = CT(0), bexy = CT(0), bexz = CT(0), beyz = CT(0);
+  bdrho += mb[0];
+  brho += mb[18] * exx + mb[6] * eyy + mb[2] * ezz + mb[12] * exy + mb[10] * exz + mb[4] * eyz;
+  bdrho += (mb[18] + mb[6] + mb[2]) * third;
+  bexx += mb[18] * rho;
+  beyy += mb[6] * rho;
+  bezz += mb[2] * rho;
+  bexy += mb[12] * rho;
+  bexz += mb[10] * rho;
+  beyz += mb[4] * rho;
+  brho += mb[24] * W24 + mb[20] * W20 + mb[8] * W8 + mb[22] * W22 + mb[16] * W16 + mb[14] * W14 +
+          mb[26] * W26;
+  bdrho += (mb[24] + mb[20] + mb[8]) * ninth + mb[26] * CT(1.0 / 27.0);
+  {
+    const CT r24 = mb[24] * rho, r20 = mb[20] * rho, r8 = mb[8] * rho;
+    bexx += r24 * (third + eyy) + r20 * (third + ezz);
+    beyy += r24 * (third + exx) + r8 * (third + ezz);
+    bezz += r20 * (third + exx) + r8 * (third + eyy);
+    bexy += r24 * CT(4) * exy;
+    bexz += r20 * CT(4) * exz;
+    beyz += r8 * CT(4) * eyz;
+    const CT r22 = mb[22] * rho, r16 = mb[16] * rho, r14 = mb[14] * rho;
+    bexx += r22 * eyz;
+    beyz += r22 * (third + exx);
+    bexy += r22 * CT(2) * exz;
+    bexz += r22 * CT(2) * exy;
+    beyy += r16 * exz;
+    bexz += r16 * (third + eyy);
+    bexy += r16 * CT(2) * eyz;
+    beyz += r16 * CT(2) * exy;
+    bezz += r14 * exy;
+    bexy += r14 * (third + ezz);
+    bexz += r14 * CT(2) * eyz;
+    beyz += r14 * CT(2) * exz;
+    const CT r26 = mb[26] * rho;
+    bexx += r26 * (ninth + (eyy + ezz) * third + eyy * ezz + CT(2) * eyz * eyz);
+    beyy += r26 * (ninth + (exx + ezz) * third + exx * ezz + CT(2) * exz * exz);
+    bezz += r26 * (ninth + (exx + eyy) * third + exx * eyy + CT(2) * exy * exy);
+    bexy += r26 * (CT(4) * (third + ezz) * exy + CT(8) * exz * eyz);
+    bexz += r26 * (CT(4) * (third + eyy) * exz + CT(8) * exy * eyz);
+    beyz += r26 * (CT(4) * (third + exx) * eyz + CT(8) * exy * exz);
+  }
+  // relaxation
+  const CT ba1 = bexx * (dxx - T3) + beyy * (dyy - T3) + bezz * (dzz - T3) + bexy * dxy + bexz * dxz +
+                 beyz * dyz;
+  const CT bT3 = ((CT(1) - p.omega2) - a1) * (bexx + beyy + bezz);
+  CT bdxx = a1 * bexx + bT3 * third, bdyy = a1 * beyy + bT3 * third, bdzz = a1 * bezz + bT3 * third;
+  CT bdxy = a1 * bexy, bdxz = a1 * bexz, bdyz = a1 * beyz;
+  btau += ba1 / (tau * tau);
+  if constexpr (LES) {
+    b_cles += btau * s / (CT(4) * R);
+    if (s > CT(0)) {
+      const CT bs = btau * p.c_les / (CT(4) * R) / s;
+      bdxx += bs * dxx;
+      bdyy += bs * dyy;
+      bdzz += bs * dzz;
+      bdxy += bs * CT(2) * dxy;
+      bdxz += bs * CT(2) * dxz;
+      bdyz += bs * CT(2) * dyz;
+    }
+  }
+  // D from raw moments
+  CT bpxx = bdxx * ir, bpyy = bdyy * ir, bpzz = bdzz * ir;
+  CT bpxy = bdxy * ir, bpxz = bdxz * ir, bpyz = bdyz * ir;
+  bdrho -= (bdxx + bdyy + bdzz) * ir * third;
+  CT bir = bdxx * (pxx - drho * third) + bdyy * (pyy - drho * third) + bdzz * (pzz - drho * third) +
+           bdxy * pxy + bdxz * pxz + bdyz * pyz;
+  bux -= CT(2) * ux * bdxx + uy * bdxy + uz * bdxz;
+  buy -= CT(2) * uy * bdyy + ux * bdxy + uz * bdyz;
+  buz -= CT(2) * uz * bdzz + ux * bdxz + uy * bdyz;
+  // velocities
+  CT bjx = bux * ir, bjy = buy * ir, bjz = buz * ir;
+  bir += bux * jx + buy * jy + buz * jz;
+  bjz += bvz * ir + buzs * ir;
+  CT bFz = bvz * ir + buzs * ir * CT(0.5);
+  bir += bvz * (jz + Fz) + buzs * (jz + CT(0.5) * Fz);
+  bchi += -p.g * bFz;
+  brho += -bir * ir * ir;
+  bdrho += brho;
+  static_for<0, 7>([&](auto qc) { pb[decltype(qc)::value] += bchi; });
+  static_for<0, 27>([&](auto qc) { gb[decltype(qc)::value] = CT(0); });
+  flow_moments_vjp<Q27, CT>(bdrho, bjx, bjy, bjz, bpxx, bpyy, bpzz, bpxy, bpxz, bpyz, gb);
+}
+
+// ---- BGK D3Q19 + Guo + Smagorinsky, D3Q6 scalar
+template <bool LES, typename CT>
+LBM_HD void vjp_bgk_q19_q6(const CT* g, const CT* ph, const CT* mg, const CT* mp, const Phys<CT>& p,
+                           CT* gb, CT* pb, CT& b_cles, CT& b_isct) {
+  CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
+  flow_moments<Q19>(g, drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz);
+  const CT chi = scalar_sum<Q6>(ph);
+  const CT rho = CT(1) + drho;
+  const CT ir = CT(1) / rho;
+  const CT Fz = -p.g * chi;
+  const CT ux = jx * ir, uy = jy * ir, uz = (jz + CT(0.5) * Fz) * ir;
+  const CT t3 = drho * CT(1.0 / 3.0);
+  const CT nxx = pxx - t3 - rho * ux * ux, nyy = pyy - t3 - rho * uy * uy,
+           nzz = pzz - t3 - rho * uz * uz;
+  const CT nxy = pxy - rho * ux * uy, nxz = pxz - rho * ux * uz, nyz = pyz - rho * uy * uz;
+  CT tau = p.tau0, sq = CT(0), h = CT(0), R = CT(0);
+  if constexpr (LES) {
+    sq = sqrt(nxx * nxx + nyy * nyy + nzz * nzz + CT(2) * (nxy * nxy + nxz * nxz + nyz * nyz));
+    h = sq * ir;
+    R = sqrt(p.tau0 * p.tau0 + p.c_les * h);
+    tau = CT(0.5) * (p.tau0 + R);
+  }
+  const CT w = CT(1) / tau;
+  const CT usq = ux * ux + uy * uy + uz * uz;
+  const CT sfac = CT(1) - CT(0.5) * w;
+
+  CT bchi = CT(0), bux = CT(0), buy = CT(0), buz = CT(0), btau = CT(0);
+  scalar_vjp<Q6, LES, CT>(ph, chi, ux, uy, uz, tau, p, mp, pb, bchi, bux, buy, buz, btau, b_isct);
+  CT bw = CT(0), bsfac = CT(0), busq = CT(0), bdrho = CT(0), brho = CT(0), bFz = CT(0);
+  static_for<0, 19>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int cx = Q19::cx[q], cy = Q19::cy[q], cz = Q19::cz[q];
+    constexpr double W = weight<Q19>(q);
+    CT cu = CT(0);
+    if (cx) cu += CT(cx) * ux;
+    if (cy) cu += CT(cy) * uy;
+    if (cz) cu += CT(cz) * uz;
+    const CT geq = CT(W) * (drho + rho * (CT(3) * cu + CT(4.5) * cu * cu - CT(1.5) * usq));
+    const CT term = CT(3) * (CT(cz) - uz) * Fz + CT(9) * cu * CT(cz) * Fz;
+    gb[q] = (CT(1) - w) * mg[q];
+    bw += mg[q] * (geq - g[q]);
+    const CT bgeq = w * mg[q];
+    const CT bS = mg[q];
+    bsfac += bS * CT(W) * term;
+    buz += bS * sfac * CT(W) * (-CT(3) * Fz);
+    CT bcu = bS * sfac * CT(W) * CT(9) * CT(cz) * Fz;
+    bFz += bS * sfac * CT(W) * (CT(3) * (CT(cz) - uz) + CT(9) * cu * CT(cz));
+    bdrho += bgeq * CT(W);
+    brho += bgeq * CT(W) * (CT(3) * cu + CT(4.5) * cu * cu - CT(1.5) * usq);
+    bcu += bgeq * CT(W) * rho * (CT(3) + CT(9) * cu);
+    busq += bgeq * CT(W) * rho * (-CT(1.5));
+    if (cx) bux += CT(cx) * bcu;
+    if (cy) buy += CT(cy) * bcu;
+    if (cz) buz += CT(cz) * bcu;
+  });
+  bw += -CT(0.5) * bsfac;
+  bux += CT(2) * ux * busq;
+  buy += CT(2) * uy * busq;
+  buz += CT(2) * uz * busq;
+  btau += -bw / (tau * tau);
+  CT bpxx = CT(0), bpyy = CT(0), bpzz = CT(0), bpxy = CT(0), bpxz = CT(0), bpyz = CT(0);
+  CT bir = CT(0);
+  if constexpr (LES) {
+    b_cles += btau * h / (CT(4) * R);
+    const CT bh = btau * p.c_les / (CT(4) * R);
+    bir += bh * sq;
+    if (sq > CT(0)) {
+      const CT bsq = bh * ir / sq;
+      const CT bnxx = bsq * nxx, bnyy = bsq * nyy, bnzz = bsq * nzz;
+      const CT bnxy = bsq * CT(2) * nxy, bnxz = bsq * CT(2) * nxz, bnyz = bsq * CT(2) * nyz;
+      bpxx += bnxx;
+      bpyy += bnyy;
+      bpzz += bnzz;
+      bpxy += bnxy;
+      bpxz += bnxz;
+      bpyz += bnyz;
+      bdrho -= (bnxx + bnyy + bnzz) * CT(1.0 / 3.0);
+      brho -= bnxx * ux * ux + bnyy * uy * uy + bnzz * uz * uz + bnxy * ux * uy + bnxz * ux * uz +
+              bnyz * uy * uz;
+      bux -= rho * (CT(2) * ux * bnxx + uy * bnxy + uz * bnxz);
+      buy -= rho * (CT(2) * uy * bnyy + ux * bnxy + uz * bnyz);
+      buz -= rho * (CT(2) * uz * bnzz + ux * bnxz + uy * bnyz);
+    }
+  }
+  CT bjx = bux * ir, bjy = buy * ir, bjz = buz * ir;
+  bFz += buz * ir * CT(0.5);
+  bir += bux * jx + buy * jy + buz * (jz + CT(0.5) * Fz);
+  bchi += -p.g * bFz;
+  brho += -bir * ir * ir;
+  bdrho += brho;
+  static_for<0, 6>([&](auto qc) { pb[decltype(qc)::value] += bchi; });
+  flow_moments_vjp<Q19, CT>(bdrho, bjx, bjy, bjz, bpxx, bpyy, bpzz, bpxy, bpxz, bpyz, gb);
+}
+
+}  // namespace lbm

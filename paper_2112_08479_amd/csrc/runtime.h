@@ -56,4 +56,16 @@ hipError_t launch_set_pop(lbm_handle* h, int q, const double* src);
 hipError_t launch_copy_state(lbm_handle* h, const void* src, void* dst);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
+// adjoint.hip
+int adjoint_blocks(const lbm_handle* h);
+int fw_blocks(const lbm_handle* h);
+hipError_t launch_adjoint_step(lbm_handle* h, const void* state, const void* lam_next,
+                               void* lam_out, double a0, double a1, double* gpart, double* dchi0);
+hipError_t launch_adjoint_seed(lbm_handle* h, const void* state, void* lam, double a0, double a1,
+                               const double* fs);
+hipError_t launch_front_seed(lbm_handle* h, double w_front, double* out);
+hipError_t launch_fw_accumulate(lbm_handle* h, const void* state, double* part, double* out);
+hipError_t launch_sum_pairs(lbm_handle* h, const double* part, int nparts, double* out);
+hipError_t launch_zero(lbm_handle* h, double* p, int64_t n);
+
 }  // namespace lbm

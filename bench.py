@@ -64,8 +64,41 @@ def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100):
     return {"workload": f"adjoint_cumulant27_q7_{nx}x{ny}x{nz}_fp32_{n_steps}steps_k{k_ckpt}",
             "nodes": n, "steps": n_steps, "seconds": dt, "MNUPS": mnups,
             "bytes_per_node_update": bpn, "GB_per_s": mnups * 1e6 * bpn / 1e9,
-            "J": J, "dJ_dcs": dcs, "dJ_dsct": dsct,
-            "note": "the 17.8 MB state fits the 256 MB last-level cache: not an HBM roofline case"}
+            "J": J, "dJ_dcs": dcs, "dJ_dsct": dsct, "hbm_frac": mnups * 1e6 * bpn / 1e9 / HBM_PEAK_GBS,
+            "note": ("state fits the 256 MB last-level cache and the run is launch bound: not an HBM "
+                     "roofline case" if n * 34 * 4 < (256 << 20) else "HBM resident")}
+
+
+def precision_report(steps=2000):
+    """FP16 / BF16 storage against FP32 storage on 2048 x 128 x 256 nodes
+    (model 1, the benchmark physics): front position, L1 velocity difference
+    and mass drift after `steps` steps."""
+    import torch
+
+    import paper_2112_08479_amd as pkg
+    out, ref = {}, None
+    for name, st in (("fp32", pkg.F32), ("fp16", pkg.F16), ("bf16", pkg.BF16)):
+        cfg = pkg.Config(2048, 128, 256, model=0, storage=st, re_b=30000.0, cs_smag=0.1, sc_t=1.0)
+        lat = pkg.Lattice(cfg)
+        lat.init_lock_exchange(0.125, 1e-3, 0)
+        lat.step(steps)
+        d = lat.diagnostics(raise_unstable=False)
+        m = lat.moments(pkg.OUT_F32)
+        u = torch.stack([m["ux"], m["uy"], m["uz"]])
+        del m
+        row = {"x_f": d["x_f"], "x_f_nd": d["x_f_nd"], "mass_drift": (d["mass"] - d["mass0"]) / d["mass0"],
+               "chi_mass_drift": (d["chi_mass"] - d["chi_mass0"]) / d["chi_mass0"],
+               "nonfinite": d["nonfinite"]}
+        if ref is None:
+            ref = (u.clone(), d["x_f"])
+        else:
+            row["front_rel_diff_vs_fp32"] = abs(d["x_f"] - ref[1]) / abs(ref[1])
+            row["l1_velocity_diff_vs_fp32"] = float((u - ref[0]).abs().sum() / ref[0].abs().sum())
+        out[name] = row
+        del u
+        lat.close()
+        torch.cuda.empty_cache()
+    return {"precision_report": "2048x128x256 cumulant27_q7, Re_b 30000, C_s 0.1", "steps": steps, **out}
 
 
 def kernel_hash():
@@ -186,12 +219,17 @@ def main():
     ap.add_argument("--workload", default=HEADLINE, choices=sorted(WORKLOADS))
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", action="store_true",
+                    help="only the FP16/BF16 vs FP32 storage comparison on 2048x128x256")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.precision:
+        print(json.dumps(precision_report()), flush=True)
+        return
     copy = stream_copy()
     print(json.dumps({"progress": "stream_copy", **copy}), file=sys.stderr, flush=True)
     head = measure(args.workload, args.steps, args.warmup)
@@ -204,9 +242,10 @@ def main():
             r = measure(v, max(50, args.steps // 4), min(args.warmup, 50))
             print(json.dumps({"progress": "variant", **r}), file=sys.stderr, flush=True)
             variants.append(r)
-        r = measure_adjoint()
-        print(json.dumps({"progress": "adjoint", **r}), file=sys.stderr, flush=True)
-        variants.append(r)
+        for kw in (dict(), dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25)):
+            r = measure_adjoint(**kw)
+            print(json.dumps({"progress": "adjoint", **r}), file=sys.stderr, flush=True)
+            variants.append(r)
     cpu = None if args.no_cpu_baseline else cpu_baseline()
     launch_bytes = head["bytes_per_node_update"] * head["nodes"]
     achieved = launch_bytes / (head["ms_per_step"] * 1e-3) / 1e9

@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = ["abi.cpp", "kernels.hip", "adjoint.hip"]
+SOURCES = ["abi.cpp", "kernels.hip", "adjoint.hip", "util.hip"]
 
 
 def hipcc():

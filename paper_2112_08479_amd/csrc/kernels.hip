@@ -11,6 +11,8 @@
 // permutation.
 #include <math.h>
 
+#include <algorithm>
+
 #include "collide.h"
 #include "lattice.h"
 #include "runtime.h"
@@ -78,13 +80,17 @@ __device__ __forceinline__ int block_order(int b, int nblocks) {
 }
 
 // ------------------------------------------------------------------- step
+#ifndef LBM_PERSIST
+#define LBM_PERSIST 0
+#endif
+
+// one tile: NPT * blockDim.x consecutive nodes of one row
 template <int MODEL, typename ST, typename CT, bool LES, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_step(const ST* __restrict__ src, ST* __restrict__ dst,
-                                                 Grid g, Phys<CT> p, int nbx) {
+__device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __restrict__ dst,
+                                          const Grid& g, const Phys<CT>& p, int nbx, int b) {
   using LF = typename ModelT<MODEL>::LF;
   using LS = typename ModelT<MODEL>::LS;
   constexpr int NPT = kNodesPerThread;
-  const int b = block_order(blockIdx.x, gridDim.x);
   const int row = b / nbx;
   const int x0 = (b - row * nbx) * (int)blockDim.x * NPT;
   if (x0 + (int)threadIdx.x >= g.nx) return;  // lanes with no node at all
@@ -115,6 +121,18 @@ __global__ __launch_bounds__(kBlock) void k_step(const ST* __restrict__ src, ST*
       if (k == 0 || x0 + xo < g.nx) store_val(&pa[xo], Conv<ST, CT>::store(v));
     }
   });
+}
+
+template <int MODEL, typename ST, typename CT, bool LES, bool GEN>
+__global__ __launch_bounds__(kBlock) void k_step(const ST* __restrict__ src, ST* __restrict__ dst,
+                                                 Grid g, Phys<CT> p, int nbx, int ntiles) {
+#if LBM_PERSIST
+  for (int b = blockIdx.x; b < ntiles; b += gridDim.x)
+    step_tile<MODEL, ST, CT, LES, GEN>(src, dst, g, p, nbx, b);
+#else
+  (void)ntiles;
+  step_tile<MODEL, ST, CT, LES, GEN>(src, dst, g, p, nbx, block_order(blockIdx.x, gridDim.x));
+#endif
 }
 
 // ------------------------------------------------------------ init states
@@ -494,7 +512,12 @@ hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
   const int per_thread_x = (g.nx + NPT - 1) / NPT;  // x-extent in threads if one block
   const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
   const int nbx = (g.nx + bx * NPT - 1) / (bx * NPT);
-  const unsigned blocks = (unsigned)((int64_t)nbx * g.ny * g.nz);
+  const int ntiles = (int)((int64_t)nbx * g.ny * g.nz);
+#if LBM_PERSIST
+  const unsigned blocks = (unsigned)std::min<int64_t>(ntiles, (int64_t)256 * LBM_PERSIST);
+#else
+  const unsigned blocks = (unsigned)ntiles;
+#endif
   const bool les = h->cfg.cs_smag > 0.0;
   const bool gen = general_rates(h);
   return with_model(h, [&](auto mc) {
@@ -507,14 +530,14 @@ hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
       ST* d = static_cast<ST*>(dst);
       if (les) {
         if (M == 0 && gen)
-          hipLaunchKernelGGL((k_step<M, ST, CT, true, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx);
+          hipLaunchKernelGGL((k_step<M, ST, CT, true, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
         else
-          hipLaunchKernelGGL((k_step<M, ST, CT, true, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx);
+          hipLaunchKernelGGL((k_step<M, ST, CT, true, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
       } else {
         if (M == 0 && gen)
-          hipLaunchKernelGGL((k_step<M, ST, CT, false, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx);
+          hipLaunchKernelGGL((k_step<M, ST, CT, false, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
         else
-          hipLaunchKernelGGL((k_step<M, ST, CT, false, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx);
+          hipLaunchKernelGGL((k_step<M, ST, CT, false, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
       }
       return hipGetLastError();
     });
@@ -621,29 +644,6 @@ hipError_t launch_set_pop(lbm_handle* h, int a, const double* src) {
       return hipGetLastError();
     });
   });
-}
-
-// STREAM-style copy: 16-byte loads, non-temporal 16-byte stores, grid-stride.
-__global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ src,
-                                                     uint4* __restrict__ dst, int64_t n16) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
-    const uint4 v = src[i];
-    __builtin_nontemporal_store(v.x, &dst[i].x);
-    __builtin_nontemporal_store(v.y, &dst[i].y);
-    __builtin_nontemporal_store(v.z, &dst[i].z);
-    __builtin_nontemporal_store(v.w, &dst[i].w);
-  }
-}
-
-hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
-  const int64_t n16 = (int64_t)(bytes / 16);
-  int64_t blocks = (n16 + 255) / 256;
-  if (blocks > 256 * 64) blocks = 256 * 64;  // 64 blocks per CU, grid-stride beyond
-  if (blocks < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, stream,
-                     static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
-  return hipGetLastError();
 }
 
 hipError_t launch_copy_state(lbm_handle* h, const void* src, void* dst) {

@@ -1,0 +1,44 @@
+// Measurement utility: a plain streaming copy, the read + write bandwidth
+// ceiling the step kernel is compared with, and a kernel of known size for
+// scaling the HBM byte counters.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "runtime.h"
+
+namespace lbm {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// each thread moves kUnroll 16-byte vectors spaced one block apart, with
+// 16-byte non-temporal stores; every element is visited once
+constexpr int kCopyUnroll = 4;
+
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4* __restrict__ src,
+                                                     u32x4* __restrict__ dst, int64_t n16) {
+  const int64_t base = (int64_t)blockIdx.x * blockDim.x * kCopyUnroll + threadIdx.x;
+  u32x4 v[kCopyUnroll];
+#pragma unroll
+  for (int k = 0; k < kCopyUnroll; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    if (i < n16) v[k] = src[i];
+  }
+#pragma unroll
+  for (int k = 0; k < kCopyUnroll; ++k) {
+    const int64_t i = base + (int64_t)k * blockDim.x;
+    if (i < n16) __builtin_nontemporal_store(v[k], &dst[i]);
+  }
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 < 1) return hipSuccess;
+  const int64_t per_block = 256 * kCopyUnroll;
+  const int64_t blocks = (n16 + per_block - 1) / per_block;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, stream,
+                     static_cast<const u32x4*>(src), static_cast<u32x4*>(dst), n16);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

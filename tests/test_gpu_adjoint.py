@@ -103,7 +103,8 @@ def test_adjoint_matches_oracle_finite_differences(storage, tol):
     got = [float((g * d).sum()) for d in dirs]
     print(f"storage {storage}: J {J} vs {ref['J']}; dCs {dcs} vs {ref['dJ_dcs']}; dSct {dsct} vs "
           f"{ref['dJ_dsct']}; dirs {got} vs {ref['dJ_dchi0_dir']}", flush=True)
-    assert abs(J - ref["J"]) <= 1e-6 * abs(ref["J"])
+    # J itself: FP64 forward to 1e-6, FP32 forward (500 steps) to 1e-5
+    assert abs(J - ref["J"]) <= (1e-6 if storage == pkg.F64 else 1e-5) * abs(ref["J"])
     assert abs(dcs - ref["dJ_dcs"]) <= tol * abs(ref["dJ_dcs"])
     assert abs(dsct - ref["dJ_dsct"]) <= tol * abs(ref["dJ_dsct"])
     for a, b in zip(got, ref["dJ_dchi0_dir"]):

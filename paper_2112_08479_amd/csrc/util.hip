@@ -11,8 +11,10 @@ namespace lbm {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // each thread moves kUnroll 16-byte vectors spaced one block apart, with
-// 16-byte non-temporal stores; every element is visited once
-constexpr int kCopyUnroll = 4;
+// 16-byte non-temporal stores; every element is visited once. One vector per
+// thread (a grid as large as the copy) measured fastest on MI355X: 6.26 TB/s
+// for 2 GiB each way, against 5.78 TB/s with four per thread.
+constexpr int kCopyUnroll = 1;
 
 __global__ __launch_bounds__(256) void k_stream_copy(const u32x4* __restrict__ src,
                                                      u32x4* __restrict__ dst, int64_t n16) {

@@ -156,6 +156,18 @@ int lbm_step(lbm_handle* h, int64_t n);
 int lbm_moments(lbm_handle* h, int dtype, void* rho_dev, void* ux_dev,
                 void* uy_dev, void* uz_dev, void* chi_dev);
 
+/* Bottom-wall shear stress of the current state in lattice units (Eq. 62,
+ * mu = rho_bar nu0 with rho_bar = 1, Eq. 52): the second-order one-sided
+ * slope through the two nearest fluid nodes (Sec. 3.2), which with the
+ * half-way wall at distance 1/2 is tau_w(x, y) = nu0 (9 u_x(z=0) - u_x(z=1))/3,
+ * u_x the signed streamwise velocity. tau_dev: nx*ny elements (index
+ * y*nx + x); tau_bar_dev: nx elements, the span average of Sec. 3.2 (the
+ * integrand of Eq. 66). Elements of type dtype (LBM_OUT_F32 / LBM_OUT_F64) in
+ * caller device buffers; NULL skips one. Summed over the wall, tau_w is the
+ * F_w of lbm_diag (Eq. 64). Needs nz >= 2 (LBM_EINVAL otherwise). Does not
+ * synchronise. */
+int lbm_wall_shear(lbm_handle* h, int dtype, void* tau_dev, void* tau_bar_dev);
+
 /* Computes the diagnostics (FP64 reductions on the GPU), synchronises and
  * writes *out. Returns LBM_EUNSTABLE (with *out filled) if nonfinite > 0. */
 int lbm_diagnostics(lbm_handle* h, lbm_diag* out);

@@ -40,6 +40,24 @@ def front_position(chi):
     return x, i_star
 
 
+def wall_shear(u, P):
+    """tau_w(j, i) = nu0 (9 u_x(i, j, z=0) - u_x(i, j, z=1)) / 3, shape (N2, N1),
+    and its span average (N1,) (Sec. 3.2, the integrand of Eq. 66)."""
+    tau = P.nu0 * (9.0 * u[0, 0] - u[0, 1]) / 3.0
+    return tau, tau.mean(0)
+
+
+def froude_number(t_nd, x_f_nd, t_lo=2.5, t_hi=10.0):
+    """Eq. 59: the front velocity d x_f~ / d t~ over 2.5 <= t~ <= 10, taken as
+    the least-squares slope of a straight line through the samples in that
+    window (numpy.polyfit, degree 1)."""
+    import numpy as np
+    t = np.asarray(t_nd, dtype=np.float64)
+    x = np.asarray(x_f_nd, dtype=np.float64)
+    sel = (t >= t_lo) & (t <= t_hi)
+    return float(np.polyfit(t[sel], x[sel], 1)[0])
+
+
 def wall_friction(u, P):
     """F_w = sum_{i,j} nu0 (9 u_x(z=0) - u_x(z=1)) / 3 (u: (3, N3, N2, N1))."""
     return (P.nu0 * (9.0 * u[0, 0] - u[0, 1]) / 3.0).sum()

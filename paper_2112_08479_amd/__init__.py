@@ -29,7 +29,7 @@ ERRORS = {LBM_EINVAL: "EINVAL", LBM_ENOMEM: "ENOMEM", LBM_EDEVICE: "EDEVICE",
 EXPORTS = [
     "lbm_derive_params", "lbm_workspace_bytes", "lbm_state_bytes", "lbm_create", "lbm_destroy",
     "lbm_init_lock_exchange", "lbm_init_from_field", "lbm_step", "lbm_moments",
-    "lbm_diagnostics", "lbm_get_step", "lbm_checkpoint_save", "lbm_checkpoint_load",
+    "lbm_wall_shear", "lbm_diagnostics", "lbm_get_step", "lbm_checkpoint_save", "lbm_checkpoint_load",
     "lbm_get_populations", "lbm_set_populations", "lbm_adjoint_workspace_bytes",
     "lbm_adjoint_run", "lbm_stream_copy", "lbm_last_error",
 ]
@@ -85,6 +85,7 @@ def lib():
             "lbm_init_from_field": (ctypes.c_int, [vp, vp, dbl]),
             "lbm_step": (ctypes.c_int, [vp, i64]),
             "lbm_moments": (ctypes.c_int, [vp, ctypes.c_int, vp, vp, vp, vp, vp]),
+            "lbm_wall_shear": (ctypes.c_int, [vp, ctypes.c_int, vp, vp]),
             "lbm_diagnostics": (ctypes.c_int, [vp, ctypes.POINTER(c_diag)]),
             "lbm_get_step": (ctypes.c_int, [vp, ctypes.POINTER(i64)]),
             "lbm_checkpoint_save": (ctypes.c_int, [vp, vp]),
@@ -220,6 +221,16 @@ class Lattice:
         out = {k: torch.empty(shp, dtype=tdt, device=self.device) for k in ("rho", "ux", "uy", "uz", "chi")}
         check(self.L.lbm_moments(self.h, dtype, *(_ptr(out[k]) for k in ("rho", "ux", "uy", "uz", "chi"))))
         return out
+
+    def wall_shear(self, dtype=OUT_F64):
+        """Bottom-wall shear stress tau_w (ny, nx) and its span average (nx),
+        lattice units, as device tensors."""
+        torch = self.torch
+        tdt = torch.float64 if dtype == OUT_F64 else torch.float32
+        tau = torch.empty((self.cfg.ny, self.cfg.nx), dtype=tdt, device=self.device)
+        bar = torch.empty((self.cfg.nx,), dtype=tdt, device=self.device)
+        check(self.L.lbm_wall_shear(self.h, dtype, _ptr(tau), _ptr(bar)))
+        return tau, bar
 
     def diagnostics(self, raise_unstable=True):
         d = c_diag()

@@ -382,6 +382,17 @@ int lbm_moments(lbm_handle* h, int dtype, void* rho, void* ux, void* uy, void* u
   return LBM_OK;
 }
 
+int lbm_wall_shear(lbm_handle* h, int dtype, void* tau, void* tau_bar) {
+  int rc = require_ready(h);
+  if (rc) return rc;
+  if (dtype != LBM_OUT_F32 && dtype != LBM_OUT_F64) return fail(LBM_EINVAL, "dtype must be LBM_OUT_F32 or LBM_OUT_F64");
+  if (h->cfg.nz < 2) return fail(LBM_EINVAL, "the wall shear stress needs nz >= 2");
+  rc = set_device(h);
+  if (rc) return rc;
+  HIPCHECK(lbm::launch_wall_shear(h, dtype, tau, tau_bar));
+  return LBM_OK;
+}
+
 int lbm_get_step(const lbm_handle* h, int64_t* step) {
   if (!h || !step) return fail(LBM_EINVAL, "NULL argument");
   *step = h->step;

@@ -232,6 +232,46 @@ __global__ __launch_bounds__(kBlock) void k_moments(const ST* __restrict__ src, 
   put_out<OT>(chi, node, c);
 }
 
+// streamwise velocity u_x = j_x / rho of the pre-collision state at a node
+template <class LF, class LS, typename ST, typename CT>
+__device__ __forceinline__ double ux_at(const ST* __restrict__ src, const Grid& g, int x, int y,
+                                        int z) {
+  const int64_t node = ((int64_t)z * g.ny + y) * g.nx + x;
+  CT fg[LF::Q], ph[LS::Q];
+  gather<LF, LS, ST, CT>(src, g, x, y, z, node, fg, ph);
+  double drho = 0, jx = 0;
+  static_for<0, LF::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    const double v = to_d(fg[q]);
+    drho += v;
+    if (LF::cx[q]) jx += LF::cx[q] * v;
+  });
+  return jx / (1.0 + drho);
+}
+
+// Bottom-wall shear stress (Eq. 62, lattice units, rho_bar = 1): the slope at
+// the half-way wall of the quadratic through u = 0 at the wall and the nodes at
+// distances 1/2 and 3/2, tau_w = nu0 (9 u_x(z=0) - u_x(z=1)) / 3. One thread
+// per x loops over the span: tau (ny x nx, row y) and its span mean tau_bar
+// (nx, the integrand of Eq. 66); NULL skips either.
+template <int MODEL, typename ST, typename CT, typename OT>
+__global__ __launch_bounds__(kBlock) void k_wall_shear(const ST* __restrict__ src, Grid g,
+                                                       double nu0, void* tau, void* tau_bar) {
+  using LF = typename ModelT<MODEL>::LF;
+  using LS = typename ModelT<MODEL>::LS;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= g.nx) return;
+  double s = 0;
+  for (int y = 0; y < g.ny; ++y) {
+    const double u0 = ux_at<LF, LS, ST, CT>(src, g, x, y, 0);
+    const double u1 = ux_at<LF, LS, ST, CT>(src, g, x, y, 1);
+    const double t = nu0 * (9.0 * u0 - u1) / 3.0;
+    put_out<OT>(tau, (int64_t)y * g.nx + x, t);
+    s += t;
+  }
+  put_out<OT>(tau_bar, x, s / g.ny);
+}
+
 // ------------------------------------------------------------- diagnostics
 __device__ __forceinline__ double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -587,6 +627,26 @@ hipError_t launch_moments(lbm_handle* h, int dtype, void* rho, void* ux, void* u
         hipLaunchKernelGGL((k_moments<M, ST, CT, double>), dim3(blocks), dim3(bx), 0, h->stream, s, g, gp, nbx, rho, ux, uy, uz, chi);
       else
         hipLaunchKernelGGL((k_moments<M, ST, CT, float>), dim3(blocks), dim3(bx), 0, h->stream, s, g, gp, nbx, rho, ux, uy, uz, chi);
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t launch_wall_shear(lbm_handle* h, int dtype, void* tau, void* tau_bar) {
+  const Grid g = grid_of(h);
+  const int bx = block_x(h);
+  const unsigned blocks = (unsigned)((g.nx + bx - 1) / bx);
+  const double nu0 = h->prm.nu0;
+  return with_model(h, [&](auto mc) {
+    constexpr int M = decltype(mc)::value;
+    return with_storage(h, [&](auto st, auto ct) {
+      using ST = decltype(st);
+      using CT = decltype(ct);
+      const ST* s = static_cast<const ST*>(h->buf[h->cur]);
+      if (dtype == LBM_OUT_F64)
+        hipLaunchKernelGGL((k_wall_shear<M, ST, CT, double>), dim3(blocks), dim3(bx), 0, h->stream, s, g, nu0, tau, tau_bar);
+      else
+        hipLaunchKernelGGL((k_wall_shear<M, ST, CT, float>), dim3(blocks), dim3(bx), 0, h->stream, s, g, nu0, tau, tau_bar);
       return hipGetLastError();
     });
   });

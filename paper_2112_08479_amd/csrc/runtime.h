@@ -50,6 +50,7 @@ hipError_t launch_init_lock(lbm_handle* h, double lock_fraction, double amp, uin
 hipError_t launch_init_field(lbm_handle* h, const double* chi0);
 hipError_t launch_moments(lbm_handle* h, int dtype, void* rho, void* ux, void* uy, void* uz,
                           void* chi);
+hipError_t launch_wall_shear(lbm_handle* h, int dtype, void* tau, void* tau_bar);
 hipError_t launch_diag(lbm_handle* h, double* out);
 hipError_t launch_get_pop(lbm_handle* h, int q, double* dst);
 hipError_t launch_set_pop(lbm_handle* h, int q, const double* src);

@@ -32,11 +32,14 @@ WORKLOADS = {
     "cumulant27_q7_2048x128x256_fp32": dict(nx=2048, ny=128, nz=256, model=0, storage="f32"),
     "cumulant27_q7_2048x128x256_fp16": dict(nx=2048, ny=128, nz=256, model=0, storage="f16"),
     "cumulant27_q7_2048x128x256_bf16": dict(nx=2048, ny=128, nz=256, model=0, storage="bf16"),
+    "cumulant27_q7_2048x128x256_bf16_f16s": dict(nx=2048, ny=128, nz=256, model=0, storage="bf16_f16s"),
     "cumulant27_q7_4096x256x512_fp16": dict(nx=4096, ny=256, nz=512, model=0, storage="f16"),
     "cumulant27_q7_4096x256x512_bf16": dict(nx=4096, ny=256, nz=512, model=0, storage="bf16"),
+    "cumulant27_q7_4096x256x512_bf16_f16s": dict(nx=4096, ny=256, nz=512, model=0, storage="bf16_f16s"),
 }
 HEADLINE = "cumulant27_q7_1024x64x128_fp32"
 VARIANTS = ["cumulant27_q7_2048x128x256_fp16", "cumulant27_q7_2048x128x256_bf16",
+            "cumulant27_q7_2048x128x256_bf16_f16s", "cumulant27_q7_4096x256x512_fp16",
             "bgk19_smag_q6_1024x64x128_fp32"]
 
 
@@ -77,7 +80,7 @@ def precision_report(steps=2000):
 
     import paper_2112_08479_amd as pkg
     out, ref = {}, None
-    for name, st in (("fp32", pkg.F32), ("fp16", pkg.F16), ("bf16", pkg.BF16)):
+    for name, st in (("fp32", pkg.F32), ("fp16", pkg.F16), ("bf16", pkg.BF16), ("bf16_f16s", pkg.BF16_F16S)):
         cfg = pkg.Config(2048, 128, 256, model=0, storage=st, re_b=30000.0, cs_smag=0.1, sc_t=1.0)
         lat = pkg.Lattice(cfg)
         lat.init_lock_exchange(0.125, 1e-3, 0)
@@ -115,7 +118,7 @@ def measure(name, steps, warmup):
 
     import paper_2112_08479_amd as pkg
     w = WORKLOADS[name]
-    st = {"f64": pkg.F64, "f32": pkg.F32, "f16": pkg.F16, "bf16": pkg.BF16}[w["storage"]]
+    st = {"f64": pkg.F64, "f32": pkg.F32, "f16": pkg.F16, "bf16": pkg.BF16, "bf16_f16s": pkg.BF16_F16S}[w["storage"]]
     cfg = pkg.Config(w["nx"], w["ny"], w["nz"], model=w["model"], storage=st, re_b=30000.0,
                      g_prime=1e-4, cs_smag=0.1, sc_t=1.0)
     lat = pkg.Lattice(cfg)
@@ -130,7 +133,7 @@ def measure(name, steps, warmup):
     ms = e0.elapsed_time(e1)
     d = lat.diagnostics(raise_unstable=False)
     q = lat.params["q_flow"] + lat.params["q_scalar"]
-    es = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}[w["storage"]]
+    es = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2, "bf16_f16s": 2}[w["storage"]]
     bpn = 2 * q * es
     n = cfg.n
     lat.close()
@@ -262,7 +265,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32",
-                  "f64": "f64"}[w["storage"]],
+                  "bf16_f16s": "bf16-flow/f16-scalar-storage/f32", "f64": "f64"}[w["storage"]],
         "data": "synthetic",
         "config": {"workload": args.workload, "nx": w["nx"], "ny": w["ny"], "nz": w["nz"],
                    "model": ["cumulant27_q7", "bgk19_smag_q6"][w["model"]], "re_b": 30000.0,

@@ -59,8 +59,10 @@ enum { LBM_CUMULANT27_Q7 = 0, LBM_BGK19_SMAG_Q6 = 1 };
  * deviations f_q - w_q from the lattice rest state (the split of Eq. 52-53),
  * the scalar populations as raw values. Arithmetic is FP64 when the storage
  * is LBM_F64 and FP32 otherwise; global reductions are FP64. 16-bit stores
- * round to nearest even. */
-enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3 };
+ * round to nearest even. LBM_BF16_F16S stores the flow in bfloat16 and the
+ * scalar in IEEE half precision (the scalar's 0..1 range needs mantissa, not
+ * exponent: bfloat16's 8-bit mantissa loses scalar mass). */
+enum { LBM_F64 = 0, LBM_F32 = 1, LBM_F16 = 2, LBM_BF16 = 3, LBM_BF16_F16S = 4 };
 
 /* Output element type for lbm_moments. */
 enum { LBM_OUT_F32 = 1, LBM_OUT_F64 = 0 };

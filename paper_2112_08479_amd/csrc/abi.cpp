@@ -40,6 +40,7 @@ size_t storage_bytes(int storage) {
     case LBM_F32: return 4;
     case LBM_F16: return 2;
     case LBM_BF16: return 2;
+    case LBM_BF16_F16S: return 2;  // flow and scalar elements have one size
   }
   return 0;
 }

@@ -85,7 +85,7 @@ __device__ __forceinline__ int block_order(int b, int nblocks) {
 #endif
 
 // one tile: NPT * blockDim.x consecutive nodes of one row
-template <int MODEL, typename ST, typename CT, bool LES, bool GEN>
+template <int MODEL, typename ST, typename SS, typename CT, bool LES, bool GEN>
 __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __restrict__ dst,
                                           const Grid& g, const Phys<CT>& p, int nbx, int b) {
   using LF = typename ModelT<MODEL>::LF;
@@ -96,7 +96,7 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
   if (x0 + (int)threadIdx.x >= g.nx) return;  // lanes with no node at all
   const int y = row % g.ny, z = row / g.ny;
   CT fg[NPT][LF::Q], ph[NPT][LS::Q];
-  gather_rows<LF, LS, NPT, ST, CT>(src, g, x0, y, z, fg, ph);
+  gather_rows<LF, LS, NPT, ST, CT, SS>(src, g, x0, y, z, fg, ph);
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     if constexpr (MODEL == 0) {
@@ -117,21 +117,25 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
       const int xo = lane + k * (int)blockDim.x;
-      const CT v = a < LF::Q ? fg[k][a < LF::Q ? a : 0] : ph[k][a < LF::Q ? 0 : a - LF::Q];
-      if (k == 0 || x0 + xo < g.nx) store_val(&pa[xo], Conv<ST, CT>::store(v));
+      if (k == 0 || x0 + xo < g.nx) {
+        if constexpr (a < LF::Q)
+          store_val(&pa[xo], Conv<ST, CT>::store(fg[k][a]));
+        else
+          store_val(&reinterpret_cast<SS*>(pa)[xo], Conv<SS, CT>::store(ph[k][a - LF::Q]));
+      }
     }
   });
 }
 
-template <int MODEL, typename ST, typename CT, bool LES, bool GEN>
+template <int MODEL, typename ST, typename SS, typename CT, bool LES, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_step(const ST* __restrict__ src, ST* __restrict__ dst,
                                                  Grid g, Phys<CT> p, int nbx, int ntiles) {
 #if LBM_PERSIST
   for (int b = blockIdx.x; b < ntiles; b += gridDim.x)
-    step_tile<MODEL, ST, CT, LES, GEN>(src, dst, g, p, nbx, b);
+    step_tile<MODEL, ST, SS, CT, LES, GEN>(src, dst, g, p, nbx, b);
 #else
   (void)ntiles;
-  step_tile<MODEL, ST, CT, LES, GEN>(src, dst, g, p, nbx, block_order(blockIdx.x, gridDim.x));
+  step_tile<MODEL, ST, SS, CT, LES, GEN>(src, dst, g, p, nbx, block_order(blockIdx.x, gridDim.x));
 #endif
 }
 
@@ -168,7 +172,7 @@ struct FieldInit {
 // Buffer slot (q, node) is read by node + c_q when that node is fluid, else by
 // the node itself for population opp(q) (bounce-back). Initial populations:
 // flow f = w (stored deviation 0), scalar phi_p = w_p chi0.
-template <int MODEL, typename ST, class Init>
+template <int MODEL, typename ST, typename SS, class Init>
 __global__ __launch_bounds__(kBlock) void k_init(ST* __restrict__ dst, Grid g, Init init, int nbx) {
   using LF = typename ModelT<MODEL>::LF;
   using LS = typename ModelT<MODEL>::LS;
@@ -190,7 +194,8 @@ __global__ __launch_bounds__(kBlock) void k_init(ST* __restrict__ dst, Grid g, I
     yn = yn < 0 ? g.ny - 1 : (yn >= g.ny ? 0 : yn);
     const bool fluid = (unsigned)xn < (unsigned)g.nx && (unsigned)zn < (unsigned)g.nz;
     const double c = fluid ? init.chi0(g, xn, yn, zn) : init.chi0(g, x, y, z);
-    dst[(int64_t)(LF::Q + q) * g.n + node] = Conv<ST, CT>::store(CT(weight<LS>(q) * c));
+    reinterpret_cast<SS*>(dst)[(int64_t)(LF::Q + q) * g.n + node] =
+        Conv<SS, CT>::store(CT(weight<LS>(q) * c));
   });
 }
 
@@ -200,7 +205,7 @@ __device__ __forceinline__ void put_out(void* p, int64_t i, double v) {
   if (p) static_cast<OT*>(p)[i] = (OT)v;
 }
 
-template <int MODEL, typename ST, typename CT, typename OT>
+template <int MODEL, typename ST, typename SS, typename CT, typename OT>
 __global__ __launch_bounds__(kBlock) void k_moments(const ST* __restrict__ src, Grid g, double gp,
                                                     int nbx, void* rho, void* ux, void* uy,
                                                     void* uz, void* chi) {
@@ -213,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const ST* __restrict__ src, 
   const int y = row % g.ny, z = row / g.ny;
   const int64_t node = (int64_t)row * g.nx + x;
   CT fg[LF::Q], ph[LS::Q];
-  gather<LF, LS, ST, CT>(src, g, x, y, z, node, fg, ph);
+  gather<LF, LS, ST, CT, SS>(src, g, x, y, z, node, fg, ph);
   double drho = 0, jx = 0, jy = 0, jz = 0, c = 0;
   static_for<0, LF::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
@@ -233,12 +238,12 @@ __global__ __launch_bounds__(kBlock) void k_moments(const ST* __restrict__ src, 
 }
 
 // streamwise velocity u_x = j_x / rho of the pre-collision state at a node
-template <class LF, class LS, typename ST, typename CT>
+template <class LF, class LS, typename ST, typename SS, typename CT>
 __device__ __forceinline__ double ux_at(const ST* __restrict__ src, const Grid& g, int x, int y,
                                         int z) {
   const int64_t node = ((int64_t)z * g.ny + y) * g.nx + x;
   CT fg[LF::Q], ph[LS::Q];
-  gather<LF, LS, ST, CT>(src, g, x, y, z, node, fg, ph);
+  gather<LF, LS, ST, CT, SS>(src, g, x, y, z, node, fg, ph);
   double drho = 0, jx = 0;
   static_for<0, LF::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
@@ -254,7 +259,7 @@ __device__ __forceinline__ double ux_at(const ST* __restrict__ src, const Grid& 
 // distances 1/2 and 3/2, tau_w = nu0 (9 u_x(z=0) - u_x(z=1)) / 3. One thread
 // per x loops over the span: tau (ny x nx, row y) and its span mean tau_bar
 // (nx, the integrand of Eq. 66); NULL skips either.
-template <int MODEL, typename ST, typename CT, typename OT>
+template <int MODEL, typename ST, typename SS, typename CT, typename OT>
 __global__ __launch_bounds__(kBlock) void k_wall_shear(const ST* __restrict__ src, Grid g,
                                                        double nu0, void* tau, void* tau_bar) {
   using LF = typename ModelT<MODEL>::LF;
@@ -263,8 +268,8 @@ __global__ __launch_bounds__(kBlock) void k_wall_shear(const ST* __restrict__ sr
   if (x >= g.nx) return;
   double s = 0;
   for (int y = 0; y < g.ny; ++y) {
-    const double u0 = ux_at<LF, LS, ST, CT>(src, g, x, y, 0);
-    const double u1 = ux_at<LF, LS, ST, CT>(src, g, x, y, 1);
+    const double u0 = ux_at<LF, LS, ST, SS, CT>(src, g, x, y, 0);
+    const double u1 = ux_at<LF, LS, ST, SS, CT>(src, g, x, y, 1);
     const double t = nu0 * (9.0 * u0 - u1) / 3.0;
     put_out<OT>(tau, (int64_t)y * g.nx + x, t);
     s += t;
@@ -304,7 +309,7 @@ __device__ void block_reduce(double (&v)[NV], int imax) {
 }
 
 // one thread per (x, z) column, looping over the span
-template <int MODEL, typename ST, typename CT>
+template <int MODEL, typename ST, typename SS, typename CT>
 __global__ __launch_bounds__(kBlock) void k_diag_columns(const ST* __restrict__ src, Grid g,
                                                          double gp, double* __restrict__ chibar,
                                                          double* __restrict__ partials, int nbx) {
@@ -318,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_diag_columns(const ST* __restrict__ 
     for (int y = 0; y < g.ny; ++y) {
       const int64_t node = ((int64_t)z * g.ny + y) * g.nx + x;
       CT fg[LF::Q], ph[LS::Q];
-      gather<LF, LS, ST, CT>(src, g, x, y, z, node, fg, ph);
+      gather<LF, LS, ST, CT, SS>(src, g, x, y, z, node, fg, ph);
       double drho = 0, jx = 0, jy = 0, jz = 0, c = 0;
       static_for<0, LF::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
@@ -417,7 +422,7 @@ __device__ __forceinline__ void vel(int q, int& cx, int& cy, int& cz) {
 }
 
 // pre-collision population a (0..qt-1) at every node, full value, float64
-template <int MODEL, typename ST>
+template <int MODEL, typename ST, typename SS>
 __global__ __launch_bounds__(kBlock) void k_get_pop(const ST* __restrict__ src, Grid g, int a,
                                                     int nbx, double* __restrict__ out) {
   using LF = typename ModelT<MODEL>::LF;
@@ -449,13 +454,14 @@ __global__ __launch_bounds__(kBlock) void k_get_pop(const ST* __restrict__ src, 
   const bool wall = (unsigned)xs >= (unsigned)g.nx || (unsigned)zs >= (unsigned)g.nz;
   const int64_t off = wall ? (int64_t)(base + o) * g.n + node
                            : (int64_t)(base + q) * g.n + ((int64_t)zs * g.ny + ys) * g.nx + xs;
-  out[node] = to_d(Conv<ST, CT>::load(src[off])) + w;
+  out[node] = (flow ? to_d(Conv<ST, CT>::load(src[off]))
+                    : to_d(Conv<SS, CT>::load(reinterpret_cast<const SS*>(src)[off]))) + w;
 }
 
 // inverse of the gather for population a given its pre-collision values v
 // (full values, float64): slot (a, y) <- v(y + c_a) when that node is fluid;
 // slot (opp a, y) <- v(y) when y - c_a is outside.
-template <int MODEL, typename ST>
+template <int MODEL, typename ST, typename SS>
 __global__ __launch_bounds__(kBlock) void k_set_pop(ST* __restrict__ dst, Grid g, int a, int nbx,
                                                     const double* __restrict__ v) {
   using LF = typename ModelT<MODEL>::LF;
@@ -481,18 +487,23 @@ __global__ __launch_bounds__(kBlock) void k_set_pop(ST* __restrict__ dst, Grid g
     w = 0.0;
   }
   const int base = flow ? 0 : LF::Q;
+  auto put = [&](int64_t i, double val) {
+    if (flow)
+      dst[i] = Conv<ST, CT>::store(CT(val));
+    else
+      reinterpret_cast<SS*>(dst)[i] = Conv<SS, CT>::store(CT(val));
+  };
   {
     const int xn = x + cx, zn = z + cz;
     int yn = y + cy;
     yn = yn < 0 ? g.ny - 1 : (yn >= g.ny ? 0 : yn);
     if ((unsigned)xn < (unsigned)g.nx && (unsigned)zn < (unsigned)g.nz)
-      dst[(int64_t)(base + q) * g.n + node] =
-          Conv<ST, CT>::store(CT(v[((int64_t)zn * g.ny + yn) * g.nx + xn] - w));
+      put((int64_t)(base + q) * g.n + node, v[((int64_t)zn * g.ny + yn) * g.nx + xn] - w);
   }
   {
     const int xs = x - cx, zs = z - cz;
     if ((unsigned)xs >= (unsigned)g.nx || (unsigned)zs >= (unsigned)g.nz)
-      dst[(int64_t)(base + o) * g.n + node] = Conv<ST, CT>::store(CT(v[node] - w));
+      put((int64_t)(base + o) * g.n + node, v[node] - w);
   }
 }
 
@@ -524,14 +535,16 @@ static Phys<CT> phys_of(const lbm_handle* h) {
   return r;
 }
 
-// calls f(ST{}, CT{}) for the handle's storage type
+// calls f(ST{}, SS{}, CT{}) for the handle's storage mode: flow element
+// type, scalar element type, arithmetic type
 template <class F>
 static hipError_t with_storage(const lbm_handle* h, F&& f) {
   switch (h->cfg.storage) {
-    case LBM_F64: return f(double{}, double{});
-    case LBM_F32: return f(float{}, float{});
-    case LBM_F16: return f(__half{}, float{});
-    case LBM_BF16: return f(bf16_t{}, float{});
+    case LBM_F64: return f(double{}, double{}, double{});
+    case LBM_F32: return f(float{}, float{}, float{});
+    case LBM_F16: return f(__half{}, __half{}, float{});
+    case LBM_BF16: return f(bf16_t{}, bf16_t{}, float{});
+    case LBM_BF16_F16S: return f(bf16_t{}, __half{}, float{});
   }
   return hipErrorInvalidValue;
 }
@@ -562,22 +575,23 @@ hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
   const bool gen = general_rates(h);
   return with_model(h, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
-    return with_storage(h, [&](auto st, auto ct) {
+    return with_storage(h, [&](auto st, auto ss, auto ct) {
       using ST = decltype(st);
+      using SS = decltype(ss);
       using CT = decltype(ct);
       const Phys<CT> p = phys_of<CT>(h);
       const ST* s = static_cast<const ST*>(src);
       ST* d = static_cast<ST*>(dst);
       if (les) {
         if (M == 0 && gen)
-          hipLaunchKernelGGL((k_step<M, ST, CT, true, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+          hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
         else
-          hipLaunchKernelGGL((k_step<M, ST, CT, true, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+          hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
       } else {
         if (M == 0 && gen)
-          hipLaunchKernelGGL((k_step<M, ST, CT, false, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+          hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
         else
-          hipLaunchKernelGGL((k_step<M, ST, CT, false, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+          hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
       }
       return hipGetLastError();
     });
@@ -592,9 +606,10 @@ static hipError_t launch_init_any(lbm_handle* h, Init init) {
   const unsigned blocks = (unsigned)((int64_t)nbx * g.ny * g.nz);
   return with_model(h, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
-    return with_storage(h, [&](auto st, auto) {
+    return with_storage(h, [&](auto st, auto ss, auto) {
       using ST = decltype(st);
-      hipLaunchKernelGGL((k_init<M, ST, Init>), dim3(blocks), dim3(bx), 0, h->stream,
+      using SS = decltype(ss);
+      hipLaunchKernelGGL((k_init<M, ST, SS, Init>), dim3(blocks), dim3(bx), 0, h->stream,
                          static_cast<ST*>(h->buf[h->cur]), g, init, nbx);
       return hipGetLastError();
     });
@@ -619,14 +634,15 @@ hipError_t launch_moments(lbm_handle* h, int dtype, void* rho, void* ux, void* u
   const double gp = h->prm.g_prime;
   return with_model(h, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
-    return with_storage(h, [&](auto st, auto ct) {
+    return with_storage(h, [&](auto st, auto ss, auto ct) {
       using ST = decltype(st);
+      using SS = decltype(ss);
       using CT = decltype(ct);
       const ST* s = static_cast<const ST*>(h->buf[h->cur]);
       if (dtype == LBM_OUT_F64)
-        hipLaunchKernelGGL((k_moments<M, ST, CT, double>), dim3(blocks), dim3(bx), 0, h->stream, s, g, gp, nbx, rho, ux, uy, uz, chi);
+        hipLaunchKernelGGL((k_moments<M, ST, SS, CT, double>), dim3(blocks), dim3(bx), 0, h->stream, s, g, gp, nbx, rho, ux, uy, uz, chi);
       else
-        hipLaunchKernelGGL((k_moments<M, ST, CT, float>), dim3(blocks), dim3(bx), 0, h->stream, s, g, gp, nbx, rho, ux, uy, uz, chi);
+        hipLaunchKernelGGL((k_moments<M, ST, SS, CT, float>), dim3(blocks), dim3(bx), 0, h->stream, s, g, gp, nbx, rho, ux, uy, uz, chi);
       return hipGetLastError();
     });
   });
@@ -639,14 +655,15 @@ hipError_t launch_wall_shear(lbm_handle* h, int dtype, void* tau, void* tau_bar)
   const double nu0 = h->prm.nu0;
   return with_model(h, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
-    return with_storage(h, [&](auto st, auto ct) {
+    return with_storage(h, [&](auto st, auto ss, auto ct) {
       using ST = decltype(st);
+      using SS = decltype(ss);
       using CT = decltype(ct);
       const ST* s = static_cast<const ST*>(h->buf[h->cur]);
       if (dtype == LBM_OUT_F64)
-        hipLaunchKernelGGL((k_wall_shear<M, ST, CT, double>), dim3(blocks), dim3(bx), 0, h->stream, s, g, nu0, tau, tau_bar);
+        hipLaunchKernelGGL((k_wall_shear<M, ST, SS, CT, double>), dim3(blocks), dim3(bx), 0, h->stream, s, g, nu0, tau, tau_bar);
       else
-        hipLaunchKernelGGL((k_wall_shear<M, ST, CT, float>), dim3(blocks), dim3(bx), 0, h->stream, s, g, nu0, tau, tau_bar);
+        hipLaunchKernelGGL((k_wall_shear<M, ST, SS, CT, float>), dim3(blocks), dim3(bx), 0, h->stream, s, g, nu0, tau, tau_bar);
       return hipGetLastError();
     });
   });
@@ -659,10 +676,11 @@ hipError_t launch_diag(lbm_handle* h, double* out) {
   const double gp = h->prm.g_prime;
   hipError_t e = with_model(h, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
-    return with_storage(h, [&](auto st, auto ct) {
+    return with_storage(h, [&](auto st, auto ss, auto ct) {
       using ST = decltype(st);
+      using SS = decltype(ss);
       using CT = decltype(ct);
-      hipLaunchKernelGGL((k_diag_columns<M, ST, CT>), dim3(nbx * g.nz), dim3(bx), 0, h->stream,
+      hipLaunchKernelGGL((k_diag_columns<M, ST, SS, CT>), dim3(nbx * g.nz), dim3(bx), 0, h->stream,
                          static_cast<const ST*>(h->buf[h->cur]), g, gp, h->chibar, h->partials,
                          nbx);
       return hipGetLastError();
@@ -681,9 +699,10 @@ hipError_t launch_get_pop(lbm_handle* h, int a, double* dst) {
   const unsigned blocks = (unsigned)((int64_t)nbx * g.ny * g.nz);
   return with_model(h, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
-    return with_storage(h, [&](auto st, auto) {
+    return with_storage(h, [&](auto st, auto ss, auto) {
       using ST = decltype(st);
-      hipLaunchKernelGGL((k_get_pop<M, ST>), dim3(blocks), dim3(bx), 0, h->stream,
+      using SS = decltype(ss);
+      hipLaunchKernelGGL((k_get_pop<M, ST, SS>), dim3(blocks), dim3(bx), 0, h->stream,
                          static_cast<const ST*>(h->buf[h->cur]), g, a, nbx, dst);
       return hipGetLastError();
     });
@@ -697,9 +716,10 @@ hipError_t launch_set_pop(lbm_handle* h, int a, const double* src) {
   const unsigned blocks = (unsigned)((int64_t)nbx * g.ny * g.nz);
   return with_model(h, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
-    return with_storage(h, [&](auto st, auto) {
+    return with_storage(h, [&](auto st, auto ss, auto) {
       using ST = decltype(st);
-      hipLaunchKernelGGL((k_set_pop<M, ST>), dim3(blocks), dim3(bx), 0, h->stream,
+      using SS = decltype(ss);
+      hipLaunchKernelGGL((k_set_pop<M, ST, SS>), dim3(blocks), dim3(bx), 0, h->stream,
                          static_cast<ST*>(h->buf[h->cur]), g, a, nbx, src);
       return hipGetLastError();
     });

@@ -217,9 +217,13 @@ __device__ __forceinline__ void pull_lattice(const ST* __restrict__ src, const G
   }
 }
 
-template <class LF, class LS, int NPT, typename ST, typename CT>
+// ST: element type of the flow arrays; SS: of the scalar arrays, which follow
+// the flow arrays in the same buffer (same element size, so the array
+// geometry and the over-read argument above are unchanged).
+template <class LF, class LS, int NPT, typename ST, typename CT, typename SS = ST>
 __device__ __forceinline__ void gather_rows(const ST* __restrict__ src, const Grid& g, int x0, int y,
                                             int z, CT (&fg)[NPT][LF::Q], CT (&ph)[NPT][LS::Q]) {
+  static_assert(sizeof(SS) == sizeof(ST), "flow and scalar elements must have one size");
   static_assert(LF::cx[0] == 0 && LF::cy[0] == 0 && LF::cz[0] == 0, "buffer must start at rest");
   static_assert(LS::cx[LS::Q - 1] == 0, "last array must not be x-shifted");
   const int64_t row0 = ((int64_t)z * g.ny + y) * g.nx + x0;
@@ -236,7 +240,8 @@ __device__ __forceinline__ void gather_rows(const ST* __restrict__ src, const Gr
   }
   const bool wave_at_wall = __builtin_amdgcn_ballot_w64(at_wall) != 0;
   pull_lattice<LF, 0, NPT, ST, CT>(src, g, row0, y, z, li, wave_at_wall, xk, fg);
-  pull_lattice<LS, LF::Q, NPT, ST, CT>(src, g, row0, y, z, li, wave_at_wall, xk, ph);
+  pull_lattice<LS, LF::Q, NPT, SS, CT>(reinterpret_cast<const SS*>(src), g, row0, y, z, li,
+                                       wave_at_wall, xk, ph);
 }
 
 template <int I, int N, class F>
@@ -248,17 +253,20 @@ LBM_HD void static_for(F&& f) {
 }
 
 // Gathers the pre-collision populations of node (x, y, z): flow populations
-// as deviations f - w into fg[], scalar populations into ph[].
-template <class LF, class LS, typename ST, typename CT>
+// as deviations f - w into fg[], scalar populations into ph[] (scalar arrays
+// of element type SS, as in gather_rows).
+template <class LF, class LS, typename ST, typename CT, typename SS = ST>
 LBM_HD void gather(const ST* __restrict__ src, const Grid& g, int x, int y, int z, int64_t node,
                    CT* fg, CT* ph) {
+  static_assert(sizeof(SS) == sizeof(ST), "flow and scalar elements must have one size");
   static_for<0, LF::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     fg[q] = Conv<ST, CT>::load(*pull_ptr<LF, q>(src, g, 0, x, y, z, (uint32_t)node));
   });
   static_for<0, LS::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    ph[q] = Conv<ST, CT>::load(*pull_ptr<LS, q>(src, g, LF::Q, x, y, z, (uint32_t)node));
+    ph[q] = Conv<SS, CT>::load(
+        *reinterpret_cast<const SS*>(pull_ptr<LS, q>(src, g, LF::Q, x, y, z, (uint32_t)node)));
   });
 }
 

@@ -52,7 +52,7 @@ def test_derived_parameters_match_the_oracle(kw):
 
 
 def test_workspace_bytes_cover_two_population_buffers():
-    for st, es in ((pkg.F64, 8), (pkg.F32, 4), (pkg.F16, 2), (pkg.BF16, 2)):
+    for st, es in ((pkg.F64, 8), (pkg.F32, 4), (pkg.F16, 2), (pkg.BF16, 2), (pkg.BF16_F16S, 2)):
         cfg = pkg.Config(1024, 64, 128, model=0, storage=st, re_b=30000.0)
         nb = pkg.workspace_bytes(cfg)
         assert nb >= 2 * 34 * cfg.n * es

@@ -4,12 +4,15 @@
   times): after 20 steps of the lock exchange, one more step is compared with
   the oracle at sampled nodes -- gate columns, every wall, the periodic span
   edges and random interior nodes -- which the oracle computes one by one.
-* 4096 x 256 x 512 (537M nodes) with FP16 / BF16 storage: the oracle cannot
-  hold the state, so properties that hold at any size are checked: finite
-  state, conserved mass and scalar mass, a front that moved forward.
-* Precision report: FP32 / FP16 / BF16 storage against the FP64 oracle on
-  the 128 x 8 x 16 grid with the benchmark physics (Re_b = 30000, C_s = 0.1),
-  1000 steps: front position, L1 velocity error, mass drift.
+* 4096 x 256 x 512 (537M nodes) with the 16-bit storage modes: the oracle
+  cannot hold the state, so properties that hold at any size are checked:
+  finite state, conserved mass and scalar mass, a front that moved forward.
+* Precision report: FP32 / FP16 / BF16 / BF16-flow + FP16-scalar storage
+  against the FP64 oracle on the 128 x 8 x 16 grid with the benchmark physics
+  (Re_b = 30000, C_s = 0.1), 1000 steps: front position, L1 velocity error,
+  mass drift.
+* The same storage modes against FP32 storage at 2048 x 128 x 256, 2000
+  steps: the front within 1 % for FP16 and BF16-flow + FP16-scalar.
 """
 import numpy as np
 import pytest
@@ -63,7 +66,7 @@ def test_benchmark_size_one_step_sampled(model):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("storage", [pkg.F16, pkg.BF16])
+@pytest.mark.parametrize("storage", [pkg.F16, pkg.BF16, pkg.BF16_F16S])
 def test_largest_grid_16bit_invariants(storage):
     cfg = pkg.Config(4096, 256, 512, model=0, storage=storage, re_b=30000.0, cs_smag=0.1)
     lat = pkg.Lattice(cfg)
@@ -99,7 +102,7 @@ def test_precision_report_against_fp64_oracle():
     kw, om, od, od0 = _oracle_precision_reference(steps)
     uref = np.abs(om["ux"]) + np.abs(om["uy"]) + np.abs(om["uz"])
     rows = {}
-    for name, st in (("fp32", pkg.F32), ("fp16", pkg.F16), ("bf16", pkg.BF16)):
+    for name, st in (("fp32", pkg.F32), ("fp16", pkg.F16), ("bf16", pkg.BF16), ("bf16_f16s", pkg.BF16_F16S)):
         cfg = pkg.Config(storage=st, **kw)
         lat = pkg.Lattice(cfg)
         lat.init_lock_exchange(0.125, 1e-3, 0)
@@ -121,4 +124,38 @@ def test_precision_report_against_fp64_oracle():
         print(f"  {k}: {v}", flush=True)
     assert rows["fp32"]["front_rel_err"] < 1e-4 and rows["fp32"]["l1_velocity_err"] < 1e-4
     assert rows["fp16"]["front_rel_err"] <= 0.01
+    assert rows["bf16_f16s"]["front_rel_err"] <= 0.01
     assert np.isfinite(rows["bf16"]["l1_velocity_err"])
+
+
+@pytest.mark.timeout(900)
+def test_16bit_storage_against_fp32_at_one_ranks_shape():
+    """2048 x 128 x 256 (the node count of one of eight slabs of the largest
+    grid), Re_b 30000, C_s 0.1, 2000 steps: the front of FP16 and of
+    BF16-flow / FP16-scalar storage within 1 % of FP32 storage on the same
+    grid. Pure BF16 is reported, not bounded: its scalar mass drifts by a few
+    per cent and the front with it."""
+    steps, ref, rows = 2000, None, {}
+    for name, st in (("fp32", pkg.F32), ("fp16", pkg.F16), ("bf16_f16s", pkg.BF16_F16S), ("bf16", pkg.BF16)):
+        cfg = pkg.Config(2048, 128, 256, model=0, storage=st, re_b=30000.0, cs_smag=0.1, sc_t=1.0)
+        lat = pkg.Lattice(cfg)
+        lat.init_lock_exchange(0.125, 1e-3, 0)
+        lat.step(steps)
+        d = lat.diagnostics()
+        m = lat.moments(pkg.OUT_F32)
+        u = torch.stack([m["ux"], m["uy"], m["uz"]])
+        del m
+        if ref is None:
+            ref = (u, d["x_f"])
+            rows[name] = {"x_f": d["x_f"]}
+        else:
+            rows[name] = {"front_rel_diff": abs(d["x_f"] - ref[1]) / abs(ref[1]),
+                          "l1_velocity_diff": float((u - ref[0]).abs().sum() / ref[0].abs().sum()),
+                          "chi_mass_drift": (d["chi_mass"] - d["chi_mass0"]) / d["chi_mass0"]}
+            del u
+        print(f"  {name}: {rows[name]}", flush=True)
+        lat.close()
+        torch.cuda.empty_cache()
+    assert rows["fp16"]["front_rel_diff"] <= 0.01
+    assert rows["bf16_f16s"]["front_rel_diff"] <= 0.01
+    assert abs(rows["bf16_f16s"]["chi_mass_drift"]) < 0.01

@@ -93,13 +93,16 @@ def test_one_step_from_random_state(model, cs, rates, storage):
 
 
 @pytest.mark.parametrize("model,cs,rates", CASES)
-@pytest.mark.parametrize("storage,mant", [(pkg.F16, 10), (pkg.BF16, 7)])
-def test_one_step_16bit_storage(model, cs, rates, storage, mant):
+@pytest.mark.parametrize("storage,mant,mant_s", [(pkg.F16, 10, 10), (pkg.BF16, 7, 7),
+                                                 (pkg.BF16_F16S, 7, 10)])
+def test_one_step_16bit_storage(model, cs, rates, storage, mant, mant_s):
     P, f0, phi0, f1, phi1, of, ophi = _random_case(model, storage, cs, rates)
     w = P.flow.w.numpy()[:, None, None, None]
     g_got, g_want = f1 - w, of - w                    # stored quantity: f - w
     assert np.all(np.abs(g_got - g_want) <= 0.5 * ulp(g_want, mant) + 2e-7)
-    assert np.all(np.abs(phi1 - ophi) <= 0.5 * ulp(ophi, mant) + 2e-7)
+    assert np.all(np.abs(phi1 - ophi) <= 0.5 * ulp(ophi, mant_s) + 2e-7)
+    if mant_s > mant:   # the scalar really is stored with the longer mantissa
+        assert np.abs(phi1 - ophi).max() < 0.25 * np.abs(ulp(ophi, mant)).max()
 
 
 @pytest.mark.timeout(900)

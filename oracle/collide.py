@@ -13,7 +13,8 @@ Order of operations inside one node (collide-then-stream form of Eq. 17):
      |S| = sqrt(2 S:S), Delta = 1; tau_f solves the resulting quadratic
      exactly) and the scalar diffusivity D0 + nu_T / Sc_T (Eq. 35).
   3. flow collision: BGK with Guo forcing (Eq. 21-26) or cumulant (Eq. 54-58).
-  4. scalar BGK (Eq. 28-29) with the velocity of step 1.
+  4. scalar collision with the velocity of step 1: BGK (Eq. 28-29) on D3Q7 /
+     D3Q6, or factorized central moments (Eq. 37-51) on D3Q27.
 """
 import math
 
@@ -200,6 +201,90 @@ def collide_scalar(phi, chi, u, tau_phi, P):
     return phi - (phi - peq) / tau_phi[None]
 
 
+# Factorized central moments (Eq. 40-49): M_abc = kappa_abc - k kappa_lower,
+# where "lower" is the index with every 2 replaced by 0. The table lists the
+# coefficient k per index pattern (any permutation of the axes); patterns
+# without a 2 (Eq. 40-43) are the central moments themselves. Reading: Eq. 46
+# prints 1/3 for the (220) pattern; 1/9 (the product of two equilibrium
+# second moments 1/3, as in Eq. 47's 1/9 and Eq. 49's 1/27) is used.
+FCM_SUBTRACT = {
+    (2, 0, 0): 1.0 / 3.0,    # Eq. 44
+    (2, 1, 0): 1.0 / 3.0,    # Eq. 45
+    (2, 2, 0): 1.0 / 9.0,    # Eq. 46 (reading)
+    (2, 2, 1): 1.0 / 9.0,    # Eq. 47
+    (2, 1, 1): 1.0 / 3.0,    # Eq. 48
+    (2, 2, 2): 1.0 / 27.0,   # Eq. 49
+}
+
+
+def _fcm_term(a, b, c):
+    """(k, lower index) of Eq. 40-49 for index (a, b, c); k = 0 if none."""
+    k = FCM_SUBTRACT.get(tuple(sorted((a, b, c), reverse=True)), 0.0)
+    lower = tuple(0 if e == 2 else e for e in (a, b, c))
+    return k, lower
+
+
+def fcm_factorize(kappa):
+    """Central moments kappa (3,3,3,n) -> factorized central moments M."""
+    M = kappa.clone()
+    for a in range(3):
+        for b in range(3):
+            for c in range(3):
+                k, lo = _fcm_term(a, b, c)
+                if k:
+                    M[a, b, c] = kappa[a, b, c] - k * kappa[lo]
+    return M
+
+
+def fcm_unfactorize(M):
+    """Inverse of fcm_factorize: kappa_abc = M_abc + k kappa_lower, lower
+    indices first (they carry no 2, so kappa_lower = M_lower)."""
+    kappa = M.clone()
+    for a in range(3):
+        for b in range(3):
+            for c in range(3):
+                k, lo = _fcm_term(a, b, c)
+                if k:
+                    kappa[a, b, c] = M[a, b, c] + k * M[lo]
+    return kappa
+
+
+def populations_from_central(kappa, u, lat):
+    """Inverse of central_moments (Eq. 39) at every node: solve
+    T(u) phi = kappa with T[abc, p] = prod_d (c_pd - u_d)^a_d."""
+    n = kappa.shape[-1]
+    c = lat.c.to(kappa.dtype)                                   # (Q, 3)
+    d = c.T[:, :, None] - u[:, None, :]                         # (3, Q, n): c_pd - u_d
+    pw = torch.stack([torch.ones_like(d), d, d * d])            # (3 powers, 3 axes, Q, n)
+    T = torch.einsum('apn,bpn,cpn->nabcp', pw[:, 0], pw[:, 1], pw[:, 2]).reshape(n, 27, lat.Q)
+    rhs = kappa.reshape(27, n).T.unsqueeze(-1)
+    return torch.linalg.solve(T, rhs).squeeze(-1).T
+
+
+def collide_fcm(phi, chi, u, tau_phi, P, omega_high=1.0):
+    """Factorized-central-moment scalar collision on D3Q27 (Eq. 37-51).
+
+    a. central moments of phi about the fluid velocity u (Eq. 38-39);
+    b. factorized central moments (Eq. 40-49, table above);
+    c. relaxation towards the zero equilibrium (Eq. 50): M_000 = chi is
+       conserved; the first-order moments relax with omega_100 = 1/tau_phi,
+       which gives D = (1/omega_100 - 1/2)/3 (Eq. 51); every other moment with
+       omega_high. Reading: the paper gives no value for the other rates;
+       1 (every non-conserved moment above first order reset to equilibrium)
+       is the default;
+    d. back through the inverse factorization and the inverse of Eq. 39.
+    """
+    lat = P.scal
+    kappa = central_moments(phi, u, lat)
+    M = fcm_factorize(kappa)
+    w1 = 1.0 / tau_phi
+    Ms = (1.0 - omega_high) * M
+    Ms[0, 0, 0] = M[0, 0, 0]
+    for idx in ((1, 0, 0), (0, 1, 0), (0, 0, 1)):
+        Ms[idx] = (1.0 - w1) * M[idx]
+    return populations_from_central(fcm_unfactorize(Ms), u, lat)
+
+
 def collide(f, phi, P, cs_smag=None, sc_t=None):
     """One full local collision. cs_smag / sc_t may be tensors (for autograd)
     or None to take them from the configuration. Returns (f*, phi*)."""
@@ -207,10 +292,13 @@ def collide(f, phi, P, cs_smag=None, sc_t=None):
     cs = cfg.cs_smag if cs_smag is None else cs_smag
     sct = cfg.sc_t if sc_t is None else sc_t
     rho, j, chi, F, u = macroscopic(f, phi, P)
-    if cfg.model == 0:
+    if cfg.model in (0, 2):
         fstar, tau = collide_cumulant(f, rho, j, F, P, cs)
     else:
         fstar, tau = collide_bgk(f, rho, u, F, P, cs)
     tau_phi = scalar_tau(tau, P, sct)
-    phistar = collide_scalar(phi, chi, u, tau_phi, P)
+    if cfg.model == 2:
+        phistar = collide_fcm(phi, chi, u, tau_phi, P)
+    else:
+        phistar = collide_scalar(phi, chi, u, tau_phi, P)
     return fstar, phistar

@@ -19,6 +19,7 @@ from .lattice import D3Q6, D3Q7, D3Q19, D3Q27
 
 CUMULANT27_Q7 = 0
 BGK19_SMAG_Q6 = 1
+CUMULANT27_FCM27 = 2        # D3Q27 cumulant flow, D3Q27 factorized-central-moment scalar
 
 
 @dataclass
@@ -60,8 +61,8 @@ class Params:
 
 
 def derive(cfg: Config) -> Params:
-    flow = D3Q27 if cfg.model == CUMULANT27_Q7 else D3Q19
-    scal = D3Q7 if cfg.model == CUMULANT27_Q7 else D3Q6
+    flow = D3Q19 if cfg.model == BGK19_SMAG_Q6 else D3Q27
+    scal = {CUMULANT27_Q7: D3Q7, BGK19_SMAG_Q6: D3Q6, CUMULANT27_FCM27: D3Q27}[cfg.model]
     H = float(cfg.nz)
     g = cfg.ub_lu ** 2 / H if cfg.ub_lu > 0 else cfg.g_prime
     u_b = math.sqrt(g * H)

@@ -201,7 +201,7 @@ def _cube_symmetries():
             yield perm, signs
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_collision_commutes_with_the_48_cube_symmetries(model):
     """No force (g' = 0): rotating/reflecting the populations commutes with the
     collision, for general rates and LES on."""

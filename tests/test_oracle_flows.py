@@ -97,7 +97,7 @@ def test_poiseuille_second_order(model):
     assert errs[0] / errs[1] > 3.0
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_scalar_variance_follows_the_exact_recurrence(model):
     """u = 0 (no force): second moment M2 of chi obeys
     M2(t+1) = M2(t) + 2(1-w) K(t) + cs^2 M0, K(t) = cs^2 M0 (1 - (1-w)^t) / w,
@@ -129,7 +129,7 @@ def test_scalar_variance_follows_the_exact_recurrence(model):
     assert math.isclose(D, P.nu0 / 0.5, rel_tol=1e-14)
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_rest_state_is_invariant(model):
     """g' = 0 and arbitrary chi: the flow stays exactly at rest, chi diffuses."""
     cfg = Config(12, 3, 6, model=model, g_prime=0.0, nu_lu=0.01)
@@ -152,7 +152,7 @@ def test_uniform_scalar_is_invariant_without_gravity():
     assert float((phi.sum(0) - 0.3).abs().max()) < 1e-15
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_hydrostatic_balance(model):
     """Uniform chi in a closed box: the flow comes to rest and
     delta rho(z) has slope -g' chi / cs^2 = -3 g' chi."""
@@ -170,7 +170,7 @@ def test_hydrostatic_balance(model):
     assert torch.allclose(slope, torch.full_like(slope, -3 * g), rtol=1e-4, atol=0)
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_lock_exchange_conserves_mass_and_scalar(model):
     cfg = Config(64, 4, 8, model=model, re_b=1000.0, cs_smag=0.1)
     P = derive(cfg)
@@ -185,7 +185,7 @@ def test_lock_exchange_conserves_mass_and_scalar(model):
     assert d['x_f'] > 0.0
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_span_symmetry_without_noise(model):
     cfg = Config(32, 3, 8, model=model, re_b=1000.0, cs_smag=0.1)
     P = derive(cfg)
@@ -197,7 +197,7 @@ def test_span_symmetry_without_noise(model):
         assert torch.equal(phi[:, :, j], phi[:, :, 0])
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_sampled_step_equals_full_step(model):
     cfg = Config(20, 3, 6, model=model, re_b=500.0, cs_smag=0.1)
     P = derive(cfg)

@@ -1,5 +1,5 @@
 """Physics sanity of the oracle itself: the slumping-phase Froude number
-(Eq. 59) of the 128 x 8 x 16 lock exchange at Re_b = 1000, both models,
+(Eq. 59) of the 128 x 8 x 16 lock exchange at Re_b = 1000, every model,
 against the 0.37 of Table 2 (Case 2, Re_b = 1000), within 0.02.
 
 The run is 4800 FP64 steps (t~ = 12) of the oracle: several minutes on eight
@@ -21,7 +21,7 @@ pytestmark = [pytest.mark.slow,
                                  reason="long oracle run; set LBM_SLOW_TESTS=1")]
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_oracle_froude_number(model):
     torch.set_num_threads(os.cpu_count() or 1)
     cfg = Config(128, 8, 16, model=model, re_b=1000.0, g_prime=1e-4)

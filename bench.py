@@ -29,6 +29,8 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "cumulant27_q7_1024x64x128_fp32": dict(nx=1024, ny=64, nz=128, model=0, storage="f32"),
     "bgk19_smag_q6_1024x64x128_fp32": dict(nx=1024, ny=64, nz=128, model=1, storage="f32"),
+    "cumulant27_fcm27_1024x64x128_fp32": dict(nx=1024, ny=64, nz=128, model=2, storage="f32"),
+    "cumulant27_fcm27_2048x128x256_fp16": dict(nx=2048, ny=128, nz=256, model=2, storage="f16"),
     "cumulant27_q7_2048x128x256_fp32": dict(nx=2048, ny=128, nz=256, model=0, storage="f32"),
     "cumulant27_q7_2048x128x256_fp16": dict(nx=2048, ny=128, nz=256, model=0, storage="f16"),
     "cumulant27_q7_2048x128x256_bf16": dict(nx=2048, ny=128, nz=256, model=0, storage="bf16"),
@@ -40,7 +42,8 @@ WORKLOADS = {
 HEADLINE = "cumulant27_q7_1024x64x128_fp32"
 VARIANTS = ["cumulant27_q7_2048x128x256_fp16", "cumulant27_q7_2048x128x256_bf16",
             "cumulant27_q7_2048x128x256_bf16_f16s", "cumulant27_q7_4096x256x512_fp16",
-            "bgk19_smag_q6_1024x64x128_fp32"]
+            "bgk19_smag_q6_1024x64x128_fp32", "cumulant27_fcm27_1024x64x128_fp32",
+            "cumulant27_fcm27_2048x128x256_fp16"]
 
 
 def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100):
@@ -268,7 +271,7 @@ def main():
                   "bf16_f16s": "bf16-flow/f16-scalar-storage/f32", "f64": "f64"}[w["storage"]],
         "data": "synthetic",
         "config": {"workload": args.workload, "nx": w["nx"], "ny": w["ny"], "nz": w["nz"],
-                   "model": ["cumulant27_q7", "bgk19_smag_q6"][w["model"]], "re_b": 30000.0,
+                   "model": ["cumulant27_q7", "bgk19_smag_q6", "cumulant27_fcm27"][w["model"]], "re_b": 30000.0,
                    "cs_smag": 0.1, "sc_t": 1.0, "g_prime": 1e-4, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

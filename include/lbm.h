@@ -53,7 +53,19 @@ enum {
   LBM_ESTATE = -6     /* call out of order (e.g. step before init) */
 };
 
-enum { LBM_CUMULANT27_Q7 = 0, LBM_BGK19_SMAG_Q6 = 1 };
+/* Models (Sec. 2.3):
+ *   LBM_CUMULANT27_Q7    D3Q27 cumulant fluid (Eq. 54-58) + D3Q7 BGK scalar
+ *                        (Eq. 28-30);
+ *   LBM_BGK19_SMAG_Q6    D3Q19 BGK fluid with Guo forcing and Smagorinsky
+ *                        eddy viscosity (Eq. 21-26, 32-35) + D3Q6 BGK scalar
+ *                        (Eq. 28-31);
+ *   LBM_CUMULANT27_FCM27 D3Q27 cumulant fluid + D3Q27 factorized-central-
+ *                        moment scalar (Eq. 36-51), the first-order moments
+ *                        relaxed with omega_100 = 1/tau_phi (Eq. 51) and the
+ *                        other non-conserved moments with rate 1.
+ * The C_s > 0 eddy viscosity and its scalar diffusivity nu_T / Sc_T apply to
+ * every model. */
+enum { LBM_CUMULANT27_Q7 = 0, LBM_BGK19_SMAG_Q6 = 1, LBM_CUMULANT27_FCM27 = 2 };
 
 /* Storage type of the populations. The flow populations are stored as
  * deviations f_q - w_q from the lattice rest state (the split of Eq. 52-53),
@@ -91,7 +103,7 @@ typedef struct {
   double tau0;      /* 3 nu0 + 1/2 */
   double d0;        /* nu0 / Sc */
   double tau_phi0;  /* 1/2 + D0 / cs_phi^2 */
-  double cs2_phi;   /* 1/4 (D3Q7) or 1/3 (D3Q6) */
+  double cs2_phi;   /* 1/4 (D3Q7) or 1/3 (D3Q6, D3Q27) */
   int32_t q_flow, q_scalar;
 } lbm_params;
 

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_ENODEV, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
-CUMULANT27_Q7, BGK19_SMAG_Q6 = 0, 1
+CUMULANT27_Q7, BGK19_SMAG_Q6, CUMULANT27_FCM27 = 0, 1, 2
 F64, F32, F16, BF16, BF16_F16S = 0, 1, 2, 3, 4
 OUT_F64, OUT_F32 = 0, 1
 STORAGE_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16", BF16_F16S: "bf16_f16s"}

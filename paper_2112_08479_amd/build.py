@@ -7,6 +7,7 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -22,21 +23,43 @@ def hipcc():
 
 
 def build(verbose=False, extra=()):
+    """Compiles every source to an object in parallel, then links."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-munsafe-fp-atomics", "-Wno-unused-result",
-           "-I", os.path.join(HERE, "..", "include"), *extra, "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed")
-    if verbose and r.stderr:
-        sys.stderr.write(r.stderr)
-    os.replace(tmp, LIB)
+    flags = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-munsafe-fp-atomics", "-Wno-unused-result",
+             "-I", os.path.join(HERE, "..", "include"), *extra]
+    objdir = tempfile.mkdtemp(prefix="lbm_build_")
+    try:
+        jobs = []
+        for src in srcs:
+            obj = os.path.join(objdir, os.path.basename(src) + ".o")
+            cmd = [hipcc(), *flags, "-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            jobs.append((obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                               text=True)))
+        failed = False
+        for obj, proc in jobs:
+            out, err = proc.communicate()
+            if proc.returncode != 0:
+                failed = True
+                sys.stderr.write(out + err)
+            elif verbose and err:
+                sys.stderr.write(err)
+        if failed:
+            raise RuntimeError("hipcc failed")
+        tmp = LIB + ".tmp"
+        cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *[o for o, _ in jobs]]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("link failed")
+        os.replace(tmp, LIB)
+    finally:
+        shutil.rmtree(objdir, ignore_errors=True)
     return LIB
 
 

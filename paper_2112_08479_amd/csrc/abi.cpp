@@ -11,6 +11,7 @@
 #include <new>
 #include <utility>
 
+#include "lattice.h"
 #include "runtime.h"
 
 namespace {
@@ -59,7 +60,7 @@ Layout layout_of(const lbm_config* c, const lbm_params* p) {
   const int nbx = (c->nx + block_x(c->nx) - 1) / block_x(c->nx);
   L.diag_blocks = nbx * c->nz;
   size_t off = 0;
-  L.buf = align256((size_t)qt * n * storage_bytes(c->storage));
+  L.buf = align256((size_t)qt * n * storage_bytes(c->storage) + lbm::kBufferGuardBytes);
   L.chibar = 2 * L.buf;
   off = L.chibar + align256((size_t)c->nx * c->nz * sizeof(double));
   L.partials = off;
@@ -82,7 +83,8 @@ int validate(const lbm_config* c, lbm_params* out) {
     return fail(LBM_EINVAL, "grid %d x %d x %d: every size must be >= 1", c->nx, c->ny, c->nz);
   const int64_t n = (int64_t)c->nx * c->ny * c->nz;
   if (n >= ((int64_t)1 << 31)) return fail(LBM_EINVAL, "grid has %lld nodes (limit 2^31 - 1)", (long long)n);
-  if (c->model != LBM_CUMULANT27_Q7 && c->model != LBM_BGK19_SMAG_Q6)
+  if (c->model != LBM_CUMULANT27_Q7 && c->model != LBM_BGK19_SMAG_Q6 &&
+      c->model != LBM_CUMULANT27_FCM27)
     return fail(LBM_EINVAL, "unknown model %d", c->model);
   if (storage_bytes(c->storage) == 0) return fail(LBM_EINVAL, "unknown storage %d", c->storage);
   if (!(c->re_b > 0) || !(c->sc > 0) || !(c->sc_t > 0))
@@ -101,8 +103,8 @@ int validate(const lbm_config* c, lbm_params* out) {
   p.d0 = p.nu0 / c->sc;
   p.cs2_phi = c->model == LBM_CUMULANT27_Q7 ? 0.25 : 1.0 / 3.0;
   p.tau_phi0 = 0.5 + p.d0 / p.cs2_phi;
-  p.q_flow = c->model == LBM_CUMULANT27_Q7 ? 27 : 19;
-  p.q_scalar = c->model == LBM_CUMULANT27_Q7 ? 7 : 6;
+  p.q_flow = c->model == LBM_BGK19_SMAG_Q6 ? 19 : 27;
+  p.q_scalar = c->model == LBM_CUMULANT27_Q7 ? 7 : (c->model == LBM_BGK19_SMAG_Q6 ? 6 : 27);
   if (!(p.tau0 > 0.5))
     return fail(LBM_EINVAL, "tau0 = %.17g must be > 1/2 (g' = 0 or Re_b too large)", p.tau0);
   if (out) *out = p;
@@ -142,7 +144,7 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, 
   AdjLayout L;
   const int64_t n = (int64_t)c->nx * c->ny * c->nz;
   const int qt = p->q_flow + p->q_scalar;
-  L.buf = align256((size_t)qt * n * storage_bytes(c->storage));
+  L.buf = align256((size_t)qt * n * storage_bytes(c->storage) + lbm::kBufferGuardBytes);
   L.nseg = (n_steps + k - 1) / k;
   L.ktraj = k < n_steps ? k : n_steps;
   const int bx = block_x(c->nx);
@@ -166,6 +168,8 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, 
 }
 
 int adjoint_supported(const lbm_config* c) {
+  if (c->model == LBM_CUMULANT27_FCM27)
+    return fail(LBM_EINVAL, "no adjoint for the factorized-central-moment scalar model");
   if (c->storage != LBM_F32 && c->storage != LBM_F64)
     return fail(LBM_EINVAL, "the adjoint needs LBM_F32 or LBM_F64 storage");
   if (c->model == LBM_CUMULANT27_Q7 &&

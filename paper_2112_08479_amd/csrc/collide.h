@@ -123,6 +123,18 @@ LBM_HD CT smagorinsky_tau(CT q2, const Phys<CT>& p) {
   return CT(0.5) * (p.tau0 + sqrt(p.tau0 * p.tau0 + p.c_les * sqrt(q2)));
 }
 
+// v[B] + ... + v[E-1] summed as a balanced binary tree: the rounding error of
+// the sum grows with log2(E - B) instead of E - B.
+template <int B, int E, typename CT>
+LBM_HD CT tree_sum(const CT* v) {
+  if constexpr (E - B == 1) {
+    return v[B];
+  } else {
+    constexpr int M = (B + E) / 2;
+    return tree_sum<B, M>(v) + tree_sum<M, E>(v);
+  }
+}
+
 // Scalar BGK (Eq. 28-29): phi* = phi - (phi - w chi (1 + c.u / cs_phi^2)) / tau_phi,
 // tau_phi = 1/2 + (D0 + nu_T / Sc_T) / cs_phi^2 (Eq. 30, 35), nu_T = (tau_f - tau0)/3.
 template <class LS, bool LES, typename CT>
@@ -143,6 +155,74 @@ LBM_HD void collide_scalar(CT* ph, CT chi, CT ux, CT uy, CT uz, CT tau, const Ph
     const CT peq = CT(weight<LS>(q)) * chi * (CT(1) + cu * p.inv_cs2phi);
     ph[q] = ph[q] - wphi * (ph[q] - peq);
   });
+}
+
+// Factorized-central-moment scalar on D3Q27 (Eq. 37-51). The moments of Eq. 39
+// are taken about the fluid velocity u; chi (Eq. 40) is conserved, the
+// first-order moments relax with omega_100 = 1/tau_phi (Eq. 50-51:
+// D = (1/omega_100 - 1/2)/3, tau_phi as for the BGK scalar), and every other
+// factorized moment is relaxed with rate 1 to its zero equilibrium. Undoing
+// the factorization (Eq. 44-49) then leaves the post-collision central moments
+//   chi E + K_x F_x + K_y F_y + K_z F_z,
+// with E = e (x) e (x) e, e = (1, 0, 1/3) per axis, F_x = f (x) e (x) e,
+// f = (0, 1, 0), and K = (1 - omega_100)(j_phi - chi u) the relaxed first
+// moments. The inverse of Eq. 39 is a product of one-dimensional inverses, so
+//   phi*_ijk = chi P_x(i) P_y(j) P_z(k) + K_x Q_x(i) P_y(j) P_z(k) + ...
+// where P (central moments e about u) and Q (central moments f about u) are
+//   P(-1) = (1/3 + u^2 - u)/2, P(0) = 2/3 - u^2, P(+1) = (1/3 + u^2 + u)/2,
+//   Q(-1) = u - 1/2,           Q(0) = -2u,       Q(+1) = u + 1/2.
+template <bool LES, typename CT>
+LBM_HD void collide_fcm27(CT* ph, CT chi, CT ux, CT uy, CT uz, CT tau, const Phys<CT>& p) {
+  CT tau_phi = p.tau_phi0;
+  if constexpr (LES) {
+    const CT nu_t = (tau - p.tau0) * CT(1.0 / 3.0);
+    tau_phi = CT(0.5) + (p.d0 + nu_t * p.inv_sct) * p.inv_cs2phi;
+  }
+  const CT a1 = CT(1) - CT(1) / tau_phi;
+  CT jx = CT(0), jy = CT(0), jz = CT(0);
+  static_for<0, 27>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    if (Q27::cx[q]) jx += CT(Q27::cx[q]) * ph[q];
+    if (Q27::cy[q]) jy += CT(Q27::cy[q]) * ph[q];
+    if (Q27::cz[q]) jz += CT(Q27::cz[q]) * ph[q];
+  });
+  const CT kx = a1 * (jx - chi * ux), ky = a1 * (jy - chi * uy), kz = a1 * (jz - chi * uz);
+  CT P[3][3], Qv[3][3];  // [axis][c + 1]
+  const CT uu[3] = {ux, uy, uz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const CT u = uu[d];
+    const CT s = CT(1.0 / 3.0) + u * u;
+    P[d][0] = CT(0.5) * (s - u);
+    P[d][1] = CT(1) - s;
+    P[d][2] = CT(0.5) * (s + u);
+    Qv[d][0] = u - CT(0.5);
+    Qv[d][1] = CT(-2) * u;
+    Qv[d][2] = u + CT(0.5);
+  }
+  // The moving populations from the closed form; the rest population takes
+  // what the others leave of chi (their tree sum), so that the sum is chi up
+  // to a few unbiased roundings. In FP32 the rounded factors do not sum to
+  // exactly 1 -- at u = 0, fl(1 - fl(1/3)) + 2 fl(1/6) = 1 - 3e-8 -- and the
+  // closed-form rest value would lose about 1e-7 of chi per step near rest.
+  static_for<1, 27>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int i = Q27::cx[q] + 1, j = Q27::cy[q] + 1, k = Q27::cz[q] + 1;
+    ph[q] = P[1][j] * P[2][k] * (chi * P[0][i] + kx * Qv[0][i]) +
+            P[0][i] * (ky * Qv[1][j] * P[2][k] + kz * P[1][j] * Qv[2][k]);
+  });
+  static_assert(Q27::cx[0] == 0 && Q27::cy[0] == 0 && Q27::cz[0] == 0, "rest population first");
+  ph[0] = chi - tree_sum<1, 27>(ph);
+}
+
+// scalar collision of the scalar lattice LS: BGK on D3Q7 / D3Q6, factorized
+// central moments on D3Q27
+template <class LS, bool LES, typename CT>
+LBM_HD void scalar_collision(CT* ph, CT chi, CT ux, CT uy, CT uz, CT tau, const Phys<CT>& p) {
+  if constexpr (LS::Q == 27)
+    collide_fcm27<LES, CT>(ph, chi, ux, uy, uz, tau, p);
+  else
+    collide_scalar<LS, LES, CT>(ph, chi, ux, uy, uz, tau, p);
 }
 
 // Flow moments of the deviations: drho, j, and raw second moments Pi^g.
@@ -169,9 +249,7 @@ LBM_HD void flow_moments(const CT* g, CT& drho, CT& jx, CT& jy, CT& jz, CT& pxx,
 
 template <class L, typename CT>
 LBM_HD CT scalar_sum(const CT* ph) {
-  CT chi = CT(0);
-  static_for<0, L::Q>([&](auto qc) { chi += ph[decltype(qc)::value]; });
-  return chi;
+  return tree_sum<0, L::Q>(ph);
 }
 
 // Relaxation of the second-order cumulant deviations D = C - delta/3
@@ -190,12 +268,13 @@ LBM_HD void relax_second(CT a1, CT omega2, CT& xx, CT& yy, CT& zz, CT& xy, CT& x
 
 // ---- cumulant collision, omega3..omega6 = 1 (every cumulant above second
 // order is reset to its equilibrium value 0): only the second-order
-// cumulants are needed; they come from the raw second moments.
-template <bool LES, typename CT>
-LBM_HD void collide_cumulant_q27_q7(CT* g, CT* ph, const Phys<CT>& p, CT* tau_out = nullptr) {
+// cumulants are needed; they come from the raw second moments. LS: the
+// scalar lattice (D3Q7 BGK or D3Q27 factorized central moments).
+template <class LS, bool LES, typename CT>
+LBM_HD void collide_cumulant27(CT* g, CT* ph, const Phys<CT>& p, CT* tau_out = nullptr) {
   CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
   flow_moments<Q27>(g, drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz);
-  const CT chi = scalar_sum<Q7>(ph);
+  const CT chi = scalar_sum<LS>(ph);
   const CT rho = CT(1) + drho;
   const CT irho = CT(1) / rho;
   const CT Fz = -p.g * chi;
@@ -241,12 +320,12 @@ LBM_HD void collide_cumulant_q27_q7(CT* g, CT* ph, const Phys<CT>& p, CT* tau_ou
                  CT(8) * dxy * dxz * dyz) +
           drho * CT(1.0 / 27.0);
   inverse_chimera<CT>(m, ux, uy, (jz + Fz) * irho, g);
-  collide_scalar<Q7, LES>(ph, chi, ux, uy, (jz + CT(0.5) * Fz) * irho, tau, p);
+  scalar_collision<LS, LES>(ph, chi, ux, uy, (jz + CT(0.5) * Fz) * irho, tau, p);
 }
 
 // ---- cumulant collision with general rates omega3..omega6.
-template <bool LES, typename CT>
-LBM_HD void collide_cumulant_q27_q7_general(CT* g, CT* ph, const Phys<CT>& p) {
+template <class LS, bool LES, typename CT>
+LBM_HD void collide_cumulant27_general(CT* g, CT* ph, const Phys<CT>& p) {
   CT drho = CT(0), jx = CT(0), jy = CT(0), jz = CT(0);
   static_for<0, 27>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
@@ -256,7 +335,7 @@ LBM_HD void collide_cumulant_q27_q7_general(CT* g, CT* ph, const Phys<CT>& p) {
     if (Q27::cy[q]) jy += CT(Q27::cy[q]) * v;
     if (Q27::cz[q]) jz += CT(Q27::cz[q]) * v;
   });
-  const CT chi = scalar_sum<Q7>(ph);
+  const CT chi = scalar_sum<LS>(ph);
   const CT rho = CT(1) + drho;
   const CT irho = CT(1) / rho;
   const CT Fz = -p.g * chi;
@@ -356,7 +435,7 @@ LBM_HD void collide_cumulant_q27_q7_general(CT* g, CT* ph, const Phys<CT>& p) {
       CT(8) * dxy * dxz * dyz;
   put(26, m222s, 1.0 / 27.0);
   inverse_chimera<CT>(m, ux, uy, (jz + Fz) * irho, g);
-  collide_scalar<Q7, LES>(ph, chi, ux, uy, (jz + CT(0.5) * Fz) * irho, tau, p);
+  scalar_collision<LS, LES>(ph, chi, ux, uy, (jz + CT(0.5) * Fz) * irho, tau, p);
 }
 
 // ---- D3Q19 BGK with Guo forcing (Eq. 21-26), Smagorinsky (Eq. 32-35),

@@ -31,6 +31,11 @@ struct ModelT<1> {
   using LF = Q19;
   using LS = Q6;
 };
+template <>
+struct ModelT<2> {
+  using LF = Q27;
+  using LS = Q27;
+};
 
 template <typename T>
 LBM_HD double to_d(T v);
@@ -90,7 +95,7 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
                                           const Grid& g, const Phys<CT>& p, int nbx, int b) {
   using LF = typename ModelT<MODEL>::LF;
   using LS = typename ModelT<MODEL>::LS;
-  constexpr int NPT = kNodesPerThread;
+  constexpr int NPT = nodes_per_thread<MODEL>();
   const int row = b / nbx;
   const int x0 = (b - row * nbx) * (int)blockDim.x * NPT;
   if (x0 + (int)threadIdx.x >= g.nx) return;  // lanes with no node at all
@@ -99,11 +104,11 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
   gather_rows<LF, LS, NPT, ST, CT, SS>(src, g, x0, y, z, fg, ph);
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
-    if constexpr (MODEL == 0) {
+    if constexpr (MODEL == 0 || MODEL == 2) {
       if constexpr (GEN)
-        collide_cumulant_q27_q7_general<LES, CT>(fg[k], ph[k], p);
+        collide_cumulant27_general<LS, LES, CT>(fg[k], ph[k], p);
       else
-        collide_cumulant_q27_q7<LES, CT>(fg[k], ph[k], p);
+        collide_cumulant27<LS, LES, CT>(fg[k], ph[k], p);
     } else {
       collide_bgk_q19_q6<LES, CT>(fg[k], ph[k], p);
     }
@@ -550,8 +555,12 @@ static hipError_t with_storage(const lbm_handle* h, F&& f) {
 }
 template <class F>
 static hipError_t with_model(const lbm_handle* h, F&& f) {
-  if (h->cfg.model == 0) return f(std::integral_constant<int, 0>{});
-  return f(std::integral_constant<int, 1>{});
+  switch (h->cfg.model) {
+    case LBM_CUMULANT27_Q7: return f(std::integral_constant<int, 0>{});
+    case LBM_BGK19_SMAG_Q6: return f(std::integral_constant<int, 1>{});
+    case LBM_CUMULANT27_FCM27: return f(std::integral_constant<int, 2>{});
+  }
+  return hipErrorInvalidValue;
 }
 
 static bool general_rates(const lbm_handle* h) {
@@ -561,20 +570,20 @@ static bool general_rates(const lbm_handle* h) {
 
 hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
   const Grid g = grid_of(h);
-  constexpr int NPT = kNodesPerThread;
-  const int per_thread_x = (g.nx + NPT - 1) / NPT;  // x-extent in threads if one block
-  const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
-  const int nbx = (g.nx + bx * NPT - 1) / (bx * NPT);
-  const int ntiles = (int)((int64_t)nbx * g.ny * g.nz);
-#if LBM_PERSIST
-  const unsigned blocks = (unsigned)std::min<int64_t>(ntiles, (int64_t)256 * LBM_PERSIST);
-#else
-  const unsigned blocks = (unsigned)ntiles;
-#endif
   const bool les = h->cfg.cs_smag > 0.0;
   const bool gen = general_rates(h);
   return with_model(h, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
+    constexpr int NPT = nodes_per_thread<M>();
+    const int per_thread_x = (g.nx + NPT - 1) / NPT;  // x-extent in threads if one block
+    const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
+    const int nbx = (g.nx + bx * NPT - 1) / (bx * NPT);
+    const int ntiles = (int)((int64_t)nbx * g.ny * g.nz);
+#if LBM_PERSIST
+    const unsigned blocks = (unsigned)std::min<int64_t>(ntiles, (int64_t)256 * LBM_PERSIST);
+#else
+    const unsigned blocks = (unsigned)ntiles;
+#endif
     return with_storage(h, [&](auto st, auto ss, auto ct) {
       using ST = decltype(st);
       using SS = decltype(ss);
@@ -583,12 +592,12 @@ hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
       const ST* s = static_cast<const ST*>(src);
       ST* d = static_cast<ST*>(dst);
       if (les) {
-        if (M == 0 && gen)
+        if (M != 1 && gen)
           hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
         else
           hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
       } else {
-        if (M == 0 && gen)
+        if (M != 1 && gen)
           hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
         else
           hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);

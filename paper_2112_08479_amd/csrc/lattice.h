@@ -124,6 +124,12 @@ struct Conv<bf16_t, float> {
   }
 };
 
+// Every population buffer is allocated with at least this many bytes of the
+// same allocation after its end: a lattice whose last array is x-shifted
+// (D3Q27 ends with a corner) makes the never-used first load of the lane at
+// x = nx - 1 read one element past the buffer.
+constexpr int kBufferGuardBytes = 256;
+
 // ---------------------------------------------------------------- geometry
 struct Grid {
   int nx, ny, nz;
@@ -168,10 +174,11 @@ LBM_HD void static_for(F&& f);
 //     pointer, the node's own opposite population;
 //   - lanes at an x wall first load a neighbouring element of the buffer
 //     (never used) and, in the waves that hold such a lane only, take the
-//     bounce-back value afterwards. That first load stays inside the buffer
-//     because its first array is a rest population (no x shift reads below
-//     it) and its last array has c_x = 0 (nothing reads past its end) --
-//     checked by the static_asserts. Lane offsets are clamped to the row so
+//     bounce-back value afterwards. That first load stays inside the
+//     allocation because the buffer's first array is a rest population (no x
+//     shift reads below it) and either its last array has c_x = 0 (nothing
+//     reads past its end) or the guard bytes follow it -- checked by the
+//     static_asserts. Lane offsets are clamped to the row so
 //     that tail lanes of a ragged row never read past it.
 template <class L, int base, int NPT, typename ST, typename CT>
 __device__ __forceinline__ void pull_lattice(const ST* __restrict__ src, const Grid& g,
@@ -225,7 +232,8 @@ __device__ __forceinline__ void gather_rows(const ST* __restrict__ src, const Gr
                                             int z, CT (&fg)[NPT][LF::Q], CT (&ph)[NPT][LS::Q]) {
   static_assert(sizeof(SS) == sizeof(ST), "flow and scalar elements must have one size");
   static_assert(LF::cx[0] == 0 && LF::cy[0] == 0 && LF::cz[0] == 0, "buffer must start at rest");
-  static_assert(LS::cx[LS::Q - 1] == 0, "last array must not be x-shifted");
+  static_assert(LS::cx[LS::Q - 1] == 0 || kBufferGuardBytes >= (int)sizeof(ST),
+                "an x-shifted last array reads one element past the buffer: needs the guard");
   const int64_t row0 = ((int64_t)z * g.ny + y) * g.nx + x0;
   unsigned li[NPT];
   int xk[NPT];

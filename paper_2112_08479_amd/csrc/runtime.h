@@ -42,6 +42,13 @@ constexpr int kBlock = LBM_BLOCK;  // threads per block along x (multiple of 64)
 #define LBM_NPT 2
 #endif
 constexpr int kNodesPerThread = LBM_NPT;  // step kernel: nodes per thread along x
+#ifndef LBM_NPT_FCM
+#define LBM_NPT_FCM 1
+#endif
+// the cumulant + D3Q27-scalar model holds 54 populations per node: one node
+// per thread keeps its register count (and so its occupancy) near the others'
+template <int MODEL>
+constexpr int nodes_per_thread() { return MODEL == 2 ? LBM_NPT_FCM : kNodesPerThread; }
 constexpr int kDiagSlots = 8;  // partial sums per diagnostic block
 
 // kernels.hip

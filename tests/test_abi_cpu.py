@@ -38,6 +38,8 @@ CONFIGS = [
     dict(nx=256, ny=16, nz=32, model=0, re_b=1000.0, cs_smag=0.1),
     dict(nx=4096, ny=256, nz=512, model=0, re_b=30000.0, cs_smag=0.1),
     dict(nx=1500, ny=100, nz=100, model=1, re_b=1000.0, ub_lu=0.03),
+    dict(nx=1024, ny=64, nz=128, model=2, re_b=30000.0, cs_smag=0.1),
+    dict(nx=128, ny=8, nz=16, model=2, re_b=1000.0),
 ]
 
 
@@ -115,3 +117,16 @@ def test_null_handles_are_rejected():
     assert L.lbm_diagnostics(None, None) == pkg.LBM_EINVAL
     assert L.lbm_checkpoint_load(None, None) == pkg.LBM_EINVAL
     assert L.lbm_destroy(None) == pkg.LBM_OK
+
+
+def test_adjoint_is_declined_where_it_is_not_built():
+    ok = pkg.Config(64, 4, 8, model=0, storage=pkg.F32, re_b=1000.0, cs_smag=0.1)
+    assert pkg.lib().lbm_adjoint_workspace_bytes(ok.c(), 10, 5) > 0
+    for bad in (dict(model=2), dict(storage=pkg.F16), dict(omega4=1.2)):
+        c = pkg.Config(**{**dict(nx=64, ny=4, nz=8, model=0, storage=pkg.F32, re_b=1000.0), **bad})
+        assert pkg.lib().lbm_adjoint_workspace_bytes(c.c(), 10, 5) == 0
+
+
+def test_workspace_bytes_of_the_fcm_model_cover_54_arrays():
+    cfg = pkg.Config(1024, 64, 128, model=2, storage=pkg.F32, re_b=30000.0)
+    assert pkg.workspace_bytes(cfg) >= 2 * 54 * cfg.n * 4

@@ -1,6 +1,6 @@
 """Parity at the benchmark sizes and the precision report.
 
-* 1024 x 64 x 128 (both models, FP32, the launch configuration bench.py
+* 1024 x 64 x 128 (every model, FP32, the launch configuration bench.py
   times): after 20 steps of the lock exchange, one more step is compared with
   the oracle at sampled nodes -- gate columns, every wall, the periodic span
   edges and random interior nodes -- which the oracle computes one by one.
@@ -43,7 +43,7 @@ def _sample_nodes(nx, ny, nz, seed=0):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_benchmark_size_one_step_sampled(model):
     cfg, P = both(pkg.F32, model=model, **BENCH)
     lat = pkg.Lattice(cfg)
@@ -62,7 +62,8 @@ def test_benchmark_size_one_step_sampled(model):
     ef = np.abs(gf - of.numpy()).max()
     ep = np.abs(gp - ophi.numpy()).max()
     print(f"model {model}: {len(nodes)} nodes, max |df| {ef:.3e}, max |dphi| {ep:.3e}", flush=True)
-    assert ef < 2e-7 and ep < 2e-7
+    # the D3Q27 scalar of model 2 has about twice the FP32 roundings
+    assert ef < 2e-7 and ep < (4e-7 if model == 2 else 2e-7)
 
 
 @pytest.mark.timeout(600)

@@ -5,7 +5,8 @@ Tolerances
                  within 1e-10 of the oracle field's infinity norm over 500
                  steps of the 128x8x16 lock exchange.
   FP32 storage : moments within 1e-5 over 100 steps (relative to each field's
-                 infinity norm); populations after one step within 2e-7.
+                 infinity norm); populations after one step within 2e-7
+                 (4e-7 for the D3Q27 scalar of model 2).
   FP16 / BF16  : one step from the same rounded state: the difference is at
                  most the final rounding (half an ulp of the 16-bit format)
                  plus FP32 arithmetic error.
@@ -49,7 +50,7 @@ def oracle_trajectory(key, P, kw, steps):
     return _cache[key]
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_initial_state_matches_oracle_bitwise(model):
     kw = dict(C0, model=model)
     cfg, P = both(pkg.F64, **kw)
@@ -79,7 +80,16 @@ def _random_case(model, storage, cs, rates, shape=(5, 3, 300), seed=1, eps=1e-2)
     return P, f0, phi0, f1, phi1, of.numpy(), ophi.numpy()
 
 
-CASES = [(0, 0.0, None), (0, 0.1, None), (0, 0.1, (1.2, 0.8, 1.3, 0.7, 1.6)), (1, 0.0, None),
+def _scalar_factor(model):
+    """The D3Q27 scalar (model 2) writes each population as a sum of four
+    triple products of values up to 0.3: about twelve FP32 roundings of
+    ulp 3e-8, against a few for the BGK scalars, so its FP32 bound is
+    doubled."""
+    return 2.0 if model == 2 else 1.0
+
+
+CASES = [(0, 0.0, None), (0, 0.1, None), (0, 0.1, (1.2, 0.8, 1.3, 0.7, 1.6)), (2, 0.0, None),
+         (2, 0.1, None), (2, 0.1, (1.2, 0.8, 1.3, 0.7, 1.6)), (1, 0.0, None),
          (1, 0.1, None)]
 
 
@@ -89,7 +99,7 @@ def test_one_step_from_random_state(model, cs, rates, storage):
     P, f0, phi0, f1, phi1, of, ophi = _random_case(model, storage, cs, rates)
     tol = 1e-13 if storage == pkg.F64 else 2e-7
     assert np.abs(f1 - of).max() < tol
-    assert np.abs(phi1 - ophi).max() < tol
+    assert np.abs(phi1 - ophi).max() < tol * _scalar_factor(model)
 
 
 @pytest.mark.parametrize("model,cs,rates", CASES)
@@ -100,13 +110,13 @@ def test_one_step_16bit_storage(model, cs, rates, storage, mant, mant_s):
     w = P.flow.w.numpy()[:, None, None, None]
     g_got, g_want = f1 - w, of - w                    # stored quantity: f - w
     assert np.all(np.abs(g_got - g_want) <= 0.5 * ulp(g_want, mant) + 2e-7)
-    assert np.all(np.abs(phi1 - ophi) <= 0.5 * ulp(ophi, mant_s) + 2e-7)
+    assert np.all(np.abs(phi1 - ophi) <= 0.5 * ulp(ophi, mant_s) + 2e-7 * _scalar_factor(model))
     if mant_s > mant:   # the scalar really is stored with the longer mantissa
         assert np.abs(phi1 - ophi).max() < 0.25 * np.abs(ulp(ophi, mant)).max()
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_lock_exchange_fp64_500_steps(model):
     """128x8x16 lock exchange, Re_b = 1000, no LES: moments within 1e-10."""
     kw = dict(C0, model=model)
@@ -133,7 +143,7 @@ def test_lock_exchange_fp64_500_steps(model):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_lock_exchange_fp32_100_steps(model):
     """Plain FP32 storage and arithmetic: moments within 1e-5 after 100 steps."""
     kw = dict(C0, model=model)
@@ -147,7 +157,7 @@ def test_lock_exchange_fp32_100_steps(model):
     assert max(errs.values()) < 1e-5, errs
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_les_trajectory_fp64(model):
     """LES on (C_s = 0.1) at Re_b = 30000 on a small grid, 60 steps."""
     kw = dict(nx=96, ny=4, nz=12, model=model, re_b=30000.0, cs_smag=0.1)
@@ -176,7 +186,7 @@ def test_checkpoint_roundtrip_is_bitwise():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 @pytest.mark.parametrize("storage", [pkg.F64, pkg.F32])
 def test_rest_state_stays_exactly_at_rest(model, storage):
     """chi = 0: no force, the flow deviations stay exactly zero."""
@@ -190,7 +200,7 @@ def test_rest_state_stays_exactly_at_rest(model, storage):
 
 
 @pytest.mark.parametrize("shape", [(1, 1, 1), (3, 4, 1), (1, 1, 5), (2, 1, 3), (4, 2, 65)])
-@pytest.mark.parametrize("model", [0, 1])
+@pytest.mark.parametrize("model", [0, 1, 2])
 def test_degenerate_and_ragged_grids(shape, model):
     """Grids of one node in some direction (every neighbour a wall or the node
     itself) and a ragged x tail: one FP64 step against the oracle."""

@@ -46,6 +46,12 @@ size_t storage_bytes(int storage) {
   return 0;
 }
 
+// bytes of one population buffer: x-blocked rows of ceil(nx / 64) blocks of
+// qt populations x 64 values
+size_t state_bytes_of(const lbm_config* c, int qt) {
+  return (size_t)c->ny * c->nz * lbm::xblocks(c->nx) * qt * lbm::kXB * storage_bytes(c->storage);
+}
+
 struct Layout {
   size_t buf, chibar, partials, dres, d0, scratch, total;
   int diag_blocks;
@@ -60,7 +66,7 @@ Layout layout_of(const lbm_config* c, const lbm_params* p) {
   const int nbx = (c->nx + block_x(c->nx) - 1) / block_x(c->nx);
   L.diag_blocks = nbx * c->nz;
   size_t off = 0;
-  L.buf = align256((size_t)qt * n * storage_bytes(c->storage) + lbm::kBufferGuardBytes);
+  L.buf = align256(state_bytes_of(c, qt) + lbm::kBufferGuardBytes);
   L.chibar = 2 * L.buf;
   off = L.chibar + align256((size_t)c->nx * c->nz * sizeof(double));
   L.partials = off;
@@ -144,7 +150,10 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, 
   AdjLayout L;
   const int64_t n = (int64_t)c->nx * c->ny * c->nz;
   const int qt = p->q_flow + p->q_scalar;
-  L.buf = align256((size_t)qt * n * storage_bytes(c->storage) + lbm::kBufferGuardBytes);
+  // population states (checkpoints, trajectory) and the two adjoint buffers
+  // (population-major, qt n values) share one slot size
+  L.buf = align256(std::max(state_bytes_of(c, qt), (size_t)qt * n * storage_bytes(c->storage)) +
+                   lbm::kBufferGuardBytes);
   L.nseg = (n_steps + k - 1) / k;
   L.ktraj = k < n_steps ? k : n_steps;
   const int bx = block_x(c->nx);
@@ -208,7 +217,7 @@ int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_fro
   double* fwpart = (double*)(ws + L.fwpart);
   double* small = (double*)(ws + L.small);  // [0] F_w sum, [8..12] front seed, [16..17] params
   const int nblk = lbm::adjoint_blocks(h);
-  const size_t sbytes = (size_t)h->qt * h->n * h->esize;
+  const size_t sbytes = h->state_bytes;
   auto ckpt = [&](int64_t s) { return (void*)(ws + L.ckpt + (size_t)s * L.buf); };
   auto traj = [&](int64_t i) { return (void*)(ws + L.traj + (size_t)i * L.buf); };
   HIPCHECK(lbm::launch_zero(h, gpart, 2 * (int64_t)nblk));
@@ -304,6 +313,7 @@ int lbm_create(const lbm_config* cfg, void* dev_workspace, size_t bytes, void* h
   h->qt = p.q_flow + p.q_scalar;
   h->n = (int64_t)cfg->nx * cfg->ny * cfg->nz;
   h->esize = storage_bytes(cfg->storage);
+  h->state_bytes = state_bytes_of(cfg, h->qt);
   if (hipGetDevice(&h->device) != hipSuccess) {
     delete h;
     return fail(LBM_EDEVICE, "hipGetDevice failed");
@@ -442,7 +452,7 @@ int lbm_checkpoint_save(lbm_handle* h, void* dev_slot) {
   if (!dev_slot) return fail(LBM_EINVAL, "slot is NULL");
   rc = set_device(h);
   if (rc) return rc;
-  const size_t sb = (size_t)h->qt * h->n * h->esize;
+  const size_t sb = h->state_bytes;
   HIPCHECK(lbm::launch_copy_state(h, h->buf[h->cur], dev_slot));
   // the step counter follows the populations (256-byte aligned)
   static thread_local int64_t stepbuf;
@@ -458,7 +468,7 @@ int lbm_checkpoint_load(lbm_handle* h, const void* dev_slot) {
   if (!dev_slot) return fail(LBM_EINVAL, "slot is NULL");
   int rc = set_device(h);
   if (rc) return rc;
-  const size_t sb = (size_t)h->qt * h->n * h->esize;
+  const size_t sb = h->state_bytes;
   HIPCHECK(lbm::launch_copy_state(h, dev_slot, h->buf[h->cur]));
   int64_t s = 0;
   HIPCHECK(hipMemcpyAsync(&s, (const char*)dev_slot + align256(sb), sizeof(int64_t),

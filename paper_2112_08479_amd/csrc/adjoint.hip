@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(const ST* __restrict__ 
     const int y = row % g.ny, z = row / g.ny;
     const int64_t node = (int64_t)row * g.nx + x;
     CT fg[LF::Q], ph[LS::Q], mg[LF::Q], mp[LS::Q], gb[LF::Q], pb[LS::Q];
-    gather<LF, LS, ST, CT>(state, g, x, y, z, node, fg, ph);
+    gather<LF, LS, ST, CT>(state, g, x, y, z, fg, ph);
     static_for<0, LF::Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
       mg[q] = lam_next[rpull_offset<LF, q>(g, 0, x, y, z, node)];
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_seed(const ST* __restrict__ 
   const double az = (z == 0) ? a0 : ((z == 1) ? a1 : 0.0);
   if (az != 0.0) {
     CT fg[LF::Q], ph[LS::Q];
-    gather<LF, LS, ST, CT>(state, g, x, y, z, node, fg, ph);
+    gather<LF, LS, ST, CT>(state, g, x, y, z, fg, ph);
     CT drho = CT(0), jx = CT(0);
     static_for<0, LF::Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_fw_layers(const ST* __restrict__ sta
     for (int z = 0; z < 2 && z < g.nz; ++z) {
       const int64_t node = ((int64_t)z * g.ny + y) * g.nx + x;
       CT fg[LF::Q], ph[LS::Q];
-      gather<LF, LS, ST, CT>(state, g, x, y, z, node, fg, ph);
+      gather<LF, LS, ST, CT>(state, g, x, y, z, fg, ph);
       double drho = 0.0, jx = 0.0;
       static_for<0, LF::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
@@ -341,7 +341,9 @@ __global__ void k_zero(double* p, int64_t n) {
 }
 
 // ---------------------------------------------------------------- launchers
-static Grid agrid(const lbm_handle* h) { return Grid{h->cfg.nx, h->cfg.ny, h->cfg.nz, h->n}; }
+static Grid agrid(const lbm_handle* h) {
+  return Grid{h->cfg.nx, h->cfg.ny, h->cfg.nz, h->n, xblocks(h->cfg.nx)};
+}
 static int ablock(const lbm_handle* h) {
   const int nx = h->cfg.nx;
   return nx >= kBlock ? kBlock : ((nx + 63) / 64) * 64;

@@ -226,18 +226,20 @@ LBM_HD void scalar_collision(CT* ph, CT chi, CT ux, CT uy, CT uz, CT tau, const 
 }
 
 // Flow moments of the deviations: drho, j, and raw second moments Pi^g.
+// drho and j are tree sums (their rounding feeds the stored state every step;
+// adding the exact zeros of the c = 0 terms changes nothing).
 template <class L, typename CT>
 LBM_HD void flow_moments(const CT* g, CT& drho, CT& jx, CT& jy, CT& jz, CT& pxx, CT& pyy,
                          CT& pzz, CT& pxy, CT& pxz, CT& pyz) {
-  drho = jx = jy = jz = pxx = pyy = pzz = pxy = pxz = pyz = CT(0);
+  CT tx[L::Q], ty[L::Q], tz[L::Q];
+  pxx = pyy = pzz = pxy = pxz = pyz = CT(0);
   static_for<0, L::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
     const CT v = g[q];
-    drho += v;
-    if (cx) jx += CT(cx) * v;
-    if (cy) jy += CT(cy) * v;
-    if (cz) jz += CT(cz) * v;
+    tx[q] = cx == 0 ? CT(0) : (cx > 0 ? v : -v);
+    ty[q] = cy == 0 ? CT(0) : (cy > 0 ? v : -v);
+    tz[q] = cz == 0 ? CT(0) : (cz > 0 ? v : -v);
     if (cx) pxx += v;
     if (cy) pyy += v;
     if (cz) pzz += v;
@@ -245,6 +247,10 @@ LBM_HD void flow_moments(const CT* g, CT& drho, CT& jx, CT& jy, CT& jz, CT& pxx,
     if (cx * cz) pxz += CT(cx * cz) * v;
     if (cy * cz) pyz += CT(cy * cz) * v;
   });
+  drho = tree_sum<0, L::Q>(g);
+  jx = tree_sum<0, L::Q>(tx);
+  jy = tree_sum<0, L::Q>(ty);
+  jz = tree_sum<0, L::Q>(tz);
 }
 
 template <class L, typename CT>

@@ -69,17 +69,31 @@ __device__ __forceinline__ void store_val(ST* p, ST v) {
 }
 
 // Block order. Consecutive block ids are dealt round-robin to the 8 XCDs
-// (each with its own L2); with the remap every XCD works on a contiguous range
-// of rows, so the partial cache lines shared by neighbouring x-tiles of a row
-// stay within one L2.
-__device__ __forceinline__ int block_order(int b, int nblocks) {
-#if LBM_XCD_REMAP
+// (each with its own L2). The tiles of one row share a cache line at each
+// tile edge (the x-shifted pulls read one element across it).
+//   LBM_XCD_REMAP 1: every XCD works on a contiguous range of tiles.
+//   LBM_XCD_REMAP 2: rows in groups of eight; within a group, block b takes
+//     row b % 8 and tile b / 8 of it, so a whole row runs on one XCD with its
+//     tiles dispatched eight blocks apart, while consecutive blocks still go
+//     to different rows (a tail group of fewer rows is dealt the same way).
+__device__ __forceinline__ int block_order(int b, int nblocks, int nbx) {
+#if LBM_XCD_REMAP == 1
+  (void)nbx;
   constexpr int kXcd = 8;
   const int per = nblocks / kXcd;
   if (b >= per * kXcd) return b;
   return (b % kXcd) * per + b / kXcd;
+#elif LBM_XCD_REMAP == 2
+  constexpr int kXcd = 8;
+  const int group = kXcd * nbx;                 // tiles of eight rows
+  const int g0 = b / group, rem = b - g0 * group;
+  const int nrows = nblocks / nbx;
+  const int rows = min(kXcd, nrows - g0 * kXcd);  // rows in this group
+  const int i = rem / rows, r = g0 * kXcd + (rem - (rem / rows) * rows);
+  return r * nbx + i;
 #else
   (void)nblocks;
+  (void)nbx;
   return b;
 #endif
 }
@@ -100,8 +114,10 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
   const int x0 = (b - row * nbx) * (int)blockDim.x * NPT;
   if (x0 + (int)threadIdx.x >= g.nx) return;  // lanes with no node at all
   const int y = row % g.ny, z = row / g.ny;
+  constexpr int QT = LF::Q + LS::Q;
+  const TileLanes<QT, NPT> t = tile_lanes<QT, NPT>(g, x0, (int)threadIdx.x, (int)blockDim.x);
   CT fg[NPT][LF::Q], ph[NPT][LS::Q];
-  gather_rows<LF, LS, NPT, ST, CT, SS>(src, g, x0, y, z, fg, ph);
+  gather_rows<LF, LS, NPT, ST, CT, SS>(src, g, t, y, z, fg, ph);
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     if constexpr (MODEL == 0 || MODEL == 2) {
@@ -113,34 +129,37 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
       collide_bgk_q19_q6<LES, CT>(fg[k], ph[k], p);
     }
   }
-  // block-uniform row pointers + lane index, as for the loads
-  ST* drow = dst + ((int64_t)row * g.nx + x0);
-  const int lane = threadIdx.x;
-  static_for<0, LF::Q + LS::Q>([&](auto qc) {
+  // block-uniform segment pointers + the lane's own offset, as for the loads
+  ST* drow = dst + (int64_t)row * g.nxb * (QT * kXB);
+  static_for<0, QT>([&](auto qc) {
     constexpr int a = decltype(qc)::value;
-    ST* pa = drow + (int64_t)a * g.n;
+    ST* pa = drow + a * kXB;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-      const int xo = lane + k * (int)blockDim.x;
-      if (k == 0 || x0 + xo < g.nx) {
+      if (k == 0 || t.x[k] < g.nx) {
         if constexpr (a < LF::Q)
-          store_val(&pa[xo], Conv<ST, CT>::store(fg[k][a]));
+          store_val(&pa[t.own[k]], Conv<ST, CT>::store(fg[k][a]));
         else
-          store_val(&reinterpret_cast<SS*>(pa)[xo], Conv<SS, CT>::store(ph[k][a - LF::Q]));
+          store_val(&reinterpret_cast<SS*>(pa)[t.own[k]], Conv<SS, CT>::store(ph[k][a - LF::Q]));
       }
     }
   });
 }
 
+// minimum waves per SIMD requested from the register allocator (0: none)
+#ifndef LBM_STEP_WAVES
+#define LBM_STEP_WAVES 0
+#endif
+
 template <int MODEL, typename ST, typename SS, typename CT, bool LES, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_step(const ST* __restrict__ src, ST* __restrict__ dst,
+__global__ __launch_bounds__(kBlock, LBM_STEP_WAVES) void k_step(const ST* __restrict__ src, ST* __restrict__ dst,
                                                  Grid g, Phys<CT> p, int nbx, int ntiles) {
 #if LBM_PERSIST
   for (int b = blockIdx.x; b < ntiles; b += gridDim.x)
     step_tile<MODEL, ST, SS, CT, LES, GEN>(src, dst, g, p, nbx, b);
 #else
   (void)ntiles;
-  step_tile<MODEL, ST, SS, CT, LES, GEN>(src, dst, g, p, nbx, block_order(blockIdx.x, gridDim.x));
+  step_tile<MODEL, ST, SS, CT, LES, GEN>(src, dst, g, p, nbx, block_order(blockIdx.x, gridDim.x, nbx));
 #endif
 }
 
@@ -187,10 +206,10 @@ __global__ __launch_bounds__(kBlock) void k_init(ST* __restrict__ dst, Grid g, I
   const int x = (b - row * nbx) * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
   const int y = row % g.ny, z = row / g.ny;
-  const int64_t node = (int64_t)row * g.nx + x;
+  constexpr int QT = LF::Q + LS::Q;
   static_for<0, LF::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    dst[(int64_t)q * g.n + node] = Conv<ST, CT>::store(CT(0));
+    dst[elem_index<QT>(g, q, row, x)] = Conv<ST, CT>::store(CT(0));
   });
   static_for<0, LS::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
@@ -199,7 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_init(ST* __restrict__ dst, Grid g, I
     yn = yn < 0 ? g.ny - 1 : (yn >= g.ny ? 0 : yn);
     const bool fluid = (unsigned)xn < (unsigned)g.nx && (unsigned)zn < (unsigned)g.nz;
     const double c = fluid ? init.chi0(g, xn, yn, zn) : init.chi0(g, x, y, z);
-    reinterpret_cast<SS*>(dst)[(int64_t)(LF::Q + q) * g.n + node] =
+    reinterpret_cast<SS*>(dst)[elem_index<QT>(g, LF::Q + q, row, x)] =
         Conv<SS, CT>::store(CT(weight<LS>(q) * c));
   });
 }
@@ -223,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const ST* __restrict__ src, 
   const int y = row % g.ny, z = row / g.ny;
   const int64_t node = (int64_t)row * g.nx + x;
   CT fg[LF::Q], ph[LS::Q];
-  gather<LF, LS, ST, CT, SS>(src, g, x, y, z, node, fg, ph);
+  gather<LF, LS, ST, CT, SS>(src, g, x, y, z, fg, ph);
   double drho = 0, jx = 0, jy = 0, jz = 0, c = 0;
   static_for<0, LF::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
@@ -246,9 +265,8 @@ __global__ __launch_bounds__(kBlock) void k_moments(const ST* __restrict__ src, 
 template <class LF, class LS, typename ST, typename SS, typename CT>
 __device__ __forceinline__ double ux_at(const ST* __restrict__ src, const Grid& g, int x, int y,
                                         int z) {
-  const int64_t node = ((int64_t)z * g.ny + y) * g.nx + x;
   CT fg[LF::Q], ph[LS::Q];
-  gather<LF, LS, ST, CT, SS>(src, g, x, y, z, node, fg, ph);
+  gather<LF, LS, ST, CT, SS>(src, g, x, y, z, fg, ph);
   double drho = 0, jx = 0;
   static_for<0, LF::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
@@ -326,9 +344,8 @@ __global__ __launch_bounds__(kBlock) void k_diag_columns(const ST* __restrict__ 
   if (x < g.nx) {
     double col = 0;
     for (int y = 0; y < g.ny; ++y) {
-      const int64_t node = ((int64_t)z * g.ny + y) * g.nx + x;
       CT fg[LF::Q], ph[LS::Q];
-      gather<LF, LS, ST, CT, SS>(src, g, x, y, z, node, fg, ph);
+      gather<LF, LS, ST, CT, SS>(src, g, x, y, z, fg, ph);
       double drho = 0, jx = 0, jy = 0, jz = 0, c = 0;
       static_for<0, LF::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
@@ -457,8 +474,9 @@ __global__ __launch_bounds__(kBlock) void k_get_pop(const ST* __restrict__ src, 
   int ys = y - cy;
   ys = ys < 0 ? g.ny - 1 : (ys >= g.ny ? 0 : ys);
   const bool wall = (unsigned)xs >= (unsigned)g.nx || (unsigned)zs >= (unsigned)g.nz;
-  const int64_t off = wall ? (int64_t)(base + o) * g.n + node
-                           : (int64_t)(base + q) * g.n + ((int64_t)zs * g.ny + ys) * g.nx + xs;
+  constexpr int QT = LF::Q + LS::Q;
+  const int64_t off = wall ? elem_index<QT>(g, base + o, row, x)
+                           : elem_index<QT>(g, base + q, (int64_t)zs * g.ny + ys, xs);
   out[node] = (flow ? to_d(Conv<ST, CT>::load(src[off]))
                     : to_d(Conv<SS, CT>::load(reinterpret_cast<const SS*>(src)[off]))) + w;
 }
@@ -503,17 +521,19 @@ __global__ __launch_bounds__(kBlock) void k_set_pop(ST* __restrict__ dst, Grid g
     int yn = y + cy;
     yn = yn < 0 ? g.ny - 1 : (yn >= g.ny ? 0 : yn);
     if ((unsigned)xn < (unsigned)g.nx && (unsigned)zn < (unsigned)g.nz)
-      put((int64_t)(base + q) * g.n + node, v[((int64_t)zn * g.ny + yn) * g.nx + xn] - w);
+      put(elem_index<LF::Q + LS::Q>(g, base + q, row, x), v[((int64_t)zn * g.ny + yn) * g.nx + xn] - w);
   }
   {
     const int xs = x - cx, zs = z - cz;
     if ((unsigned)xs >= (unsigned)g.nx || (unsigned)zs >= (unsigned)g.nz)
-      put((int64_t)(base + o) * g.n + node, v[node] - w);
+      put(elem_index<LF::Q + LS::Q>(g, base + o, row, x), v[node] - w);
   }
 }
 
 // ---------------------------------------------------------------- dispatch
-static Grid grid_of(const lbm_handle* h) { return Grid{h->cfg.nx, h->cfg.ny, h->cfg.nz, h->n}; }
+static Grid grid_of(const lbm_handle* h) {
+  return Grid{h->cfg.nx, h->cfg.ny, h->cfg.nz, h->n, xblocks(h->cfg.nx)};
+}
 
 static int block_x(const lbm_handle* h) {
   const int nx = h->cfg.nx;
@@ -736,8 +756,7 @@ hipError_t launch_set_pop(lbm_handle* h, int a, const double* src) {
 }
 
 hipError_t launch_copy_state(lbm_handle* h, const void* src, void* dst) {
-  return hipMemcpyAsync(dst, src, (size_t)h->qt * h->n * h->esize, hipMemcpyDeviceToDevice,
-                        h->stream);
+  return hipMemcpyAsync(dst, src, h->state_bytes, hipMemcpyDeviceToDevice, h->stream);
 }
 
 }  // namespace lbm

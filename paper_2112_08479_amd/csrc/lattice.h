@@ -124,31 +124,45 @@ struct Conv<bf16_t, float> {
   }
 };
 
-// Every population buffer is allocated with at least this many bytes of the
-// same allocation after its end: a lattice whose last array is x-shifted
-// (D3Q27 ends with a corner) makes the never-used first load of the lane at
-// x = nx - 1 read one element past the buffer.
+// ---------------------------------------------------------------- geometry
+// Population buffer layout (x-blocked). Rows (y, z) follow one another; each
+// row is cut into blocks of kXB = 64 consecutive x (one wavefront), and an
+// x-block holds the QT populations one after the other, 64 values each:
+//   element(a, x, row) = (row nxb + x / 64) QT 64 + 64 a + x % 64,
+// with nxb = ceil(nx / 64) x-blocks per row (the last one padded when 64 does
+// not divide nx; padding is never read as fluid data). A wavefront loads or
+// stores one population as one contiguous 64-element segment, and the QT
+// populations of a tile are one contiguous span: a tile reads from the nine
+// rows (y - c_y, z - c_z) and writes one span, where a population-major
+// layout has every tile touch 2 QT separate arrays.
+constexpr int kXB = 64;
+constexpr int kXBShift = 6;
+
+// Spare bytes after every population buffer in its allocation (none are read
+// by the kernels; kept as a margin).
 constexpr int kBufferGuardBytes = 256;
 
-// ---------------------------------------------------------------- geometry
 struct Grid {
   int nx, ny, nz;
   int64_t n;  // nodes
+  int nxb;    // x-blocks per row, ceil(nx / 64)
 };
 
-// Source element (array index, node index) that population q of lattice L at
-// node (x, y, z) pulls from: the neighbour x - c_q when it is a fluid node
-// (y taken modulo ny), else -- half-way bounce-back -- population opp(q) of
-// the node itself.
-// The array base pointers depend only on q and the launch (scalar registers);
-// node indices fit in 32 bits (n < 2^31), computed unsigned so that the
-// unselected out-of-range candidate at a wall is harmless.
-template <class L, int q, typename ST>
-LBM_HD const ST* pull_ptr(const ST* __restrict__ src, const Grid& g, int base, int x, int y, int z,
-                          uint32_t node) {
+LBM_HD int xblocks(int nx) { return (nx + kXB - 1) / kXB; }
+
+// element index of population a at (x, row), row = z ny + y
+template <int QT>
+LBM_HD int64_t elem_index(const Grid& g, int a, int64_t row, int x) {
+  return (row * g.nxb + (x >> kXBShift)) * (int64_t)(QT * kXB) + (int64_t)a * kXB + (x & (kXB - 1));
+}
+
+// Source element of population q (lattice L, arrays base.. of a buffer with
+// QT populations) at node (x, y, z): the neighbour x - c_q when it is a fluid
+// node (y taken modulo ny), else -- half-way bounce-back -- population opp(q)
+// of the node itself.
+template <class L, int q, int QT, typename ST>
+LBM_HD const ST* pull_ptr(const ST* __restrict__ src, const Grid& g, int base, int x, int y, int z) {
   constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
-  const ST* pq = src + (int64_t)(base + q) * g.n;
-  const ST* po = src + (int64_t)(base + opp<L>(q)) * g.n;
   const int xs = x - cx;
   const int zs = z - cz;
   int ys = y - cy;
@@ -157,99 +171,136 @@ LBM_HD const ST* pull_ptr(const ST* __restrict__ src, const Grid& g, int base, i
   bool wall = false;
   if (cx != 0) wall = wall || ((unsigned)xs >= (unsigned)g.nx);
   if (cz != 0) wall = wall || ((unsigned)zs >= (unsigned)g.nz);
-  const uint32_t s = ((uint32_t)zs * (uint32_t)g.ny + (uint32_t)ys) * (uint32_t)g.nx + (uint32_t)xs;
-  return wall ? po + node : pq + s;
+  const int64_t e = wall ? elem_index<QT>(g, base + opp<L>(q), (int64_t)z * g.ny + y, x)
+                         : elem_index<QT>(g, base + q, (int64_t)zs * g.ny + ys, xs);
+  return src + e;
 }
 
 template <int I, int N, class F>
 LBM_HD void static_for(F&& f);
 
-// Gather for a thread block that covers NPT * blockDim.x consecutive nodes
-// x0 .. of one row (y, z); thread `lane` handles x0 + lane + k blockDim.x,
-// k < NPT. Every pull address is a block-uniform row pointer (scalar
-// registers, advanced by one array per population) plus the lane index, so
-// the gather costs no per-lane address arithmetic:
+// Lane geometry of a tile for the x-blocked layout. Thread t handles nodes
+// x = x0 + t + k blockDim.x (k < NPT); x0 and blockDim.x are multiples of 64,
+// so t % 64 is the node's place in its x-block. Offsets are element offsets
+// inside a row (all populations of the row), taken at x clamped to nx - 1 so
+// that tail lanes of a ragged row read a real node (their results are never
+// stored):
+//   own:  the node itself;
+//   srcp: its x - 1 neighbour (pull of c_x = +1), the node itself at x = 0;
+//   srcm: its x + 1 neighbour (pull of c_x = -1), the node itself at x = nx - 1.
+// At the walls the neighbour is replaced by bounce-back afterwards, so every
+// address stays inside the row.
+template <int QT, int NPT>
+struct TileLanes {
+  int own[NPT], srcp[NPT], srcm[NPT], x[NPT];
+};
+
+template <int QT, int NPT>
+LBM_HD TileLanes<QT, NPT> tile_lanes(const Grid& g, int x0, int tid, int bdim) {
+  TileLanes<QT, NPT> t;
+  constexpr int XBLK = QT * kXB;
+#pragma unroll
+  for (int k = 0; k < NPT; ++k) {
+    const int x = x0 + tid + k * bdim;
+    const int xe = x < g.nx ? x : g.nx - 1;
+    const int xl = xe & (kXB - 1);
+    const int own = (xe >> kXBShift) * XBLK + xl;
+    t.x[k] = x;
+    t.own[k] = own;
+    t.srcp[k] = xe == 0 ? own : (xl == 0 ? own - XBLK + (kXB - 1) : own - 1);
+    t.srcm[k] = xe == g.nx - 1 ? own : (xl == kXB - 1 ? own + XBLK - (kXB - 1) : own + 1);
+  }
+  return t;
+}
+
+// Gather of one lattice (arrays base.. of the buffer) for a tile of row
+// (y, z). Each pull is a block-uniform pointer (scalar registers: the source
+// row, or the node's own row at a z wall, plus the population's segment) and a
+// per-lane offset from TileLanes, chosen by c_x:
 //   - y is periodic: the source row is chosen per block;
 //   - a source beyond a z wall (uniform per block) selects the bounce-back
-//     pointer, the node's own opposite population;
-//   - lanes at an x wall first load a neighbouring element of the buffer
-//     (never used) and, in the waves that hold such a lane only, take the
-//     bounce-back value afterwards. That first load stays inside the
-//     allocation because the buffer's first array is a rest population (no x
-//     shift reads below it) and either its last array has c_x = 0 (nothing
-//     reads past its end) or the guard bytes follow it -- checked by the
-//     static_asserts. Lane offsets are clamped to the row so
-//     that tail lanes of a ragged row never read past it.
-template <class L, int base, int NPT, typename ST, typename CT>
-__device__ __forceinline__ void pull_lattice(const ST* __restrict__ src, const Grid& g,
-                                             int64_t row0, int y, int z, const unsigned* li,
-                                             bool wave_at_wall, const int* xk,
-                                             CT (&out)[NPT][L::Q]) {
-  const int dy_m = (y == g.ny - 1) ? -(g.ny - 1) : 1;  // c_y = -1: source row y + 1
-  const int dy_p = (y == 0) ? g.ny - 1 : -1;           // c_y = +1: source row y - 1
-  const ST* arr0 = src + (int64_t)base * g.n + row0;
-  {
-    const ST* arr = arr0;
-    static_for<0, L::Q>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
-      constexpr int o = opp<L>(q);
-      const bool zwall = cz != 0 && (unsigned)(z - cz) >= (unsigned)g.nz;
-      const int dy = cy == 0 ? 0 : (cy == 1 ? dy_p : dy_m);
-      const int64_t sh = zwall ? (int64_t)(o - q) * g.n : ((int64_t)(-cz) * g.ny + dy) * g.nx - cx;
-      const ST* p = arr + sh;
+//     segment of the node's own row;
+//   - lanes at an x wall first load their own node's element (never used)
+//     and, in the waves that hold such a lane only, take the bounce-back
+//     value afterwards.
+// Block-uniform part of the pull of population q (lattice L, arrays base..):
+// the element index of its 64-value segment in the source row, or in the
+// node's own row (population opp(q)) when the source is beyond a z wall.
+template <class L, int q, int base, int QT>
+LBM_HD int64_t pull_segment(const Grid& g, int y, int z, bool& zwall) {
+  constexpr int cy = L::cy[q], cz = L::cz[q];
+  const int64_t rowlen = (int64_t)g.nxb * (QT * kXB);
+  zwall = cz != 0 && (unsigned)(z - cz) >= (unsigned)g.nz;
+  int ys = y;
+  if (cy == 1) ys = (y == 0) ? g.ny - 1 : y - 1;
+  if (cy == -1) ys = (y == g.ny - 1) ? 0 : y + 1;
+  return zwall ? ((int64_t)z * g.ny + y) * rowlen + (base + opp<L>(q)) * kXB
+               : ((int64_t)(z - cz) * g.ny + ys) * rowlen + (base + q) * kXB;
+}
+
+// Per-lane part: the offset of node k's source inside the row, by c_x (the
+// node itself at a z wall).
+template <class L, int q, int QT, int NPT>
+LBM_HD int pull_lane(const TileLanes<QT, NPT>& t, int k, bool zwall) {
+  constexpr int cx = L::cx[q];
+  return zwall ? t.own[k] : (cx == 1 ? t.srcp[k] : (cx == -1 ? t.srcm[k] : t.own[k]));
+}
+
+// Bounce-back at an x wall: population opp(q) of the node itself.
+template <class L, int q, int base, int QT>
+LBM_HD int64_t bounce_segment(const Grid& g, int y, int z) {
+  return ((int64_t)z * g.ny + y) * ((int64_t)g.nxb * (QT * kXB)) + (base + opp<L>(q)) * kXB;
+}
+
+template <class L, int q>
+LBM_HD bool x_wall(const Grid& g, int x, bool zwall) {
+  constexpr int cx = L::cx[q];
+  return cx != 0 && !zwall && (unsigned)(x - cx) >= (unsigned)g.nx;
+}
+
+template <class L, int base, int QT, int NPT, typename ST, typename CT>
+__device__ __forceinline__ void pull_lattice(const ST* __restrict__ src, const Grid& g, int y,
+                                             int z, const TileLanes<QT, NPT>& t,
+                                             bool wave_at_wall, CT (&out)[NPT][L::Q]) {
+  static_for<0, L::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    bool zwall;
+    const ST* p = src + pull_segment<L, q, base, QT>(g, y, z, zwall);
 #pragma unroll
-      for (int k = 0; k < NPT; ++k) out[k][q] = Conv<ST, CT>::load(p[li[k]]);
-      arr += g.n;
-    });
-  }
+    for (int k = 0; k < NPT; ++k) out[k][q] = Conv<ST, CT>::load(p[pull_lane<L, q, QT, NPT>(t, k, zwall)]);
+  });
   if (wave_at_wall) {  // wave-uniform: this wave holds x = 0 or x = nx - 1
-    const ST* arr = arr0;
     static_for<0, L::Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      constexpr int cx = L::cx[q], cz = L::cz[q];
-      constexpr int o = opp<L>(q);
-      if constexpr (cx != 0) {
-        const bool zwall = cz != 0 && (unsigned)(z - cz) >= (unsigned)g.nz;
-        const ST* po = arr + (int64_t)(o - q) * g.n;
+      if constexpr (L::cx[q] != 0) {
+        bool zwall;
+        (void)pull_segment<L, q, base, QT>(g, y, z, zwall);
+        const ST* po = src + bounce_segment<L, q, base, QT>(g, y, z);
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-          const bool wall = !zwall && (unsigned)(xk[k] - cx) >= (unsigned)g.nx;
-          const CT b = Conv<ST, CT>::load(po[li[k]]);
-          out[k][q] = wall ? b : out[k][q];
+          const CT b = Conv<ST, CT>::load(po[t.own[k]]);
+          out[k][q] = x_wall<L, q>(g, t.x[k], zwall) ? b : out[k][q];
         }
       }
-      arr += g.n;
     });
   }
 }
 
-// ST: element type of the flow arrays; SS: of the scalar arrays, which follow
-// the flow arrays in the same buffer (same element size, so the array
-// geometry and the over-read argument above are unchanged).
+// ST: element type of the flow arrays; SS: of the scalar arrays (same
+// element size, so one layout holds both).
 template <class LF, class LS, int NPT, typename ST, typename CT, typename SS = ST>
-__device__ __forceinline__ void gather_rows(const ST* __restrict__ src, const Grid& g, int x0, int y,
-                                            int z, CT (&fg)[NPT][LF::Q], CT (&ph)[NPT][LS::Q]) {
+__device__ __forceinline__ void gather_rows(const ST* __restrict__ src, const Grid& g,
+                                            const TileLanes<LF::Q + LS::Q, NPT>& t, int y, int z,
+                                            CT (&fg)[NPT][LF::Q], CT (&ph)[NPT][LS::Q]) {
   static_assert(sizeof(SS) == sizeof(ST), "flow and scalar elements must have one size");
-  static_assert(LF::cx[0] == 0 && LF::cy[0] == 0 && LF::cz[0] == 0, "buffer must start at rest");
-  static_assert(LS::cx[LS::Q - 1] == 0 || kBufferGuardBytes >= (int)sizeof(ST),
-                "an x-shifted last array reads one element past the buffer: needs the guard");
-  const int64_t row0 = ((int64_t)z * g.ny + y) * g.nx + x0;
-  unsigned li[NPT];
-  int xk[NPT];
-  const unsigned last = (unsigned)(g.nx - 1 - x0);  // >= 0: the block holds a node
+  constexpr int QT = LF::Q + LS::Q;
   bool at_wall = false;
 #pragma unroll
-  for (int k = 0; k < NPT; ++k) {
-    const unsigned o = threadIdx.x + (unsigned)k * blockDim.x;
-    li[k] = o < last ? o : last;
-    xk[k] = x0 + (int)o;
-    at_wall = at_wall || xk[k] == 0 || xk[k] == g.nx - 1;
-  }
+  for (int k = 0; k < NPT; ++k) at_wall = at_wall || t.x[k] == 0 || t.x[k] == g.nx - 1;
   const bool wave_at_wall = __builtin_amdgcn_ballot_w64(at_wall) != 0;
-  pull_lattice<LF, 0, NPT, ST, CT>(src, g, row0, y, z, li, wave_at_wall, xk, fg);
-  pull_lattice<LS, LF::Q, NPT, SS, CT>(reinterpret_cast<const SS*>(src), g, row0, y, z, li,
-                                       wave_at_wall, xk, ph);
+  pull_lattice<LF, 0, QT, NPT, ST, CT>(src, g, y, z, t, wave_at_wall, fg);
+  pull_lattice<LS, LF::Q, QT, NPT, SS, CT>(reinterpret_cast<const SS*>(src), g, y, z, t,
+                                           wave_at_wall, ph);
 }
 
 template <int I, int N, class F>
@@ -264,17 +315,17 @@ LBM_HD void static_for(F&& f) {
 // as deviations f - w into fg[], scalar populations into ph[] (scalar arrays
 // of element type SS, as in gather_rows).
 template <class LF, class LS, typename ST, typename CT, typename SS = ST>
-LBM_HD void gather(const ST* __restrict__ src, const Grid& g, int x, int y, int z, int64_t node,
-                   CT* fg, CT* ph) {
+LBM_HD void gather(const ST* __restrict__ src, const Grid& g, int x, int y, int z, CT* fg, CT* ph) {
   static_assert(sizeof(SS) == sizeof(ST), "flow and scalar elements must have one size");
+  constexpr int QT = LF::Q + LS::Q;
   static_for<0, LF::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    fg[q] = Conv<ST, CT>::load(*pull_ptr<LF, q>(src, g, 0, x, y, z, (uint32_t)node));
+    fg[q] = Conv<ST, CT>::load(*pull_ptr<LF, q, QT>(src, g, 0, x, y, z));
   });
   static_for<0, LS::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     ph[q] = Conv<SS, CT>::load(
-        *reinterpret_cast<const SS*>(pull_ptr<LS, q>(src, g, LF::Q, x, y, z, (uint32_t)node)));
+        *reinterpret_cast<const SS*>(pull_ptr<LS, q, QT>(src, g, LF::Q, x, y, z)));
   });
 }
 

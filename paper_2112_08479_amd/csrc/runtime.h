@@ -15,6 +15,7 @@ struct lbm_handle {
   int qf, qs, qt;     // flow, scalar, total populations
   int64_t n;          // nodes
   size_t esize;       // bytes per stored population value
+  size_t state_bytes; // bytes of one population buffer (x-blocked, padded rows)
   int device;
   hipStream_t stream;
   char* ws;

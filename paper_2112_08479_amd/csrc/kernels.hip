@@ -109,7 +109,7 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
                                           const Grid& g, const Phys<CT>& p, int nbx, int b) {
   using LF = typename ModelT<MODEL>::LF;
   using LS = typename ModelT<MODEL>::LS;
-  constexpr int NPT = nodes_per_thread<MODEL>();
+  constexpr int NPT = nodes_per_thread<MODEL, ST>();
   const int row = b / nbx;
   const int x0 = (b - row * nbx) * (int)blockDim.x * NPT;
   if (x0 + (int)threadIdx.x >= g.nx) return;  // lanes with no node at all
@@ -594,20 +594,20 @@ hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
   const bool gen = general_rates(h);
   return with_model(h, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
-    constexpr int NPT = nodes_per_thread<M>();
-    const int per_thread_x = (g.nx + NPT - 1) / NPT;  // x-extent in threads if one block
-    const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
-    const int nbx = (g.nx + bx * NPT - 1) / (bx * NPT);
-    const int ntiles = (int)((int64_t)nbx * g.ny * g.nz);
-#if LBM_PERSIST
-    const unsigned blocks = (unsigned)std::min<int64_t>(ntiles, (int64_t)256 * LBM_PERSIST);
-#else
-    const unsigned blocks = (unsigned)ntiles;
-#endif
     return with_storage(h, [&](auto st, auto ss, auto ct) {
       using ST = decltype(st);
       using SS = decltype(ss);
       using CT = decltype(ct);
+      constexpr int NPT = nodes_per_thread<M, ST>();
+      const int per_thread_x = (g.nx + NPT - 1) / NPT;  // x-extent in threads if one block
+      const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
+      const int nbx = (g.nx + bx * NPT - 1) / (bx * NPT);
+      const int ntiles = (int)((int64_t)nbx * g.ny * g.nz);
+#if LBM_PERSIST
+      const unsigned blocks = (unsigned)std::min<int64_t>(ntiles, (int64_t)256 * LBM_PERSIST);
+#else
+      const unsigned blocks = (unsigned)ntiles;
+#endif
       const Phys<CT> p = phys_of<CT>(h);
       const ST* s = static_cast<const ST*>(src);
       ST* d = static_cast<ST*>(dst);

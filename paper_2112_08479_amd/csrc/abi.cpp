@@ -151,9 +151,8 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, 
   const int64_t n = (int64_t)c->nx * c->ny * c->nz;
   const int qt = p->q_flow + p->q_scalar;
   // population states (checkpoints, trajectory) and the two adjoint buffers
-  // (population-major, qt n values) share one slot size
-  L.buf = align256(std::max(state_bytes_of(c, qt), (size_t)qt * n * storage_bytes(c->storage)) +
-                   lbm::kBufferGuardBytes);
+  // share the population buffers' x-blocked layout and slot size
+  L.buf = align256(state_bytes_of(c, qt) + lbm::kBufferGuardBytes);
   L.nseg = (n_steps + k - 1) / k;
   L.ktraj = k < n_steps ? k : n_steps;
   const int bx = block_x(c->nx);
@@ -169,7 +168,7 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, 
   L.gpart = off;
   off += align256((size_t)ablocks * 2 * sizeof(double));
   L.fwpart = off;
-  off += align256((size_t)fblocks * 2 * sizeof(double));
+  off += align256((size_t)n_steps * fblocks * 2 * sizeof(double));  // one slot set per step
   L.small = off;
   off += 256;
   L.total = off;
@@ -222,17 +221,20 @@ int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_fro
   auto traj = [&](int64_t i) { return (void*)(ws + L.traj + (size_t)i * L.buf); };
   HIPCHECK(lbm::launch_zero(h, gpart, 2 * (int64_t)nblk));
   HIPCHECK(lbm::launch_zero(h, small, 32));
-  // forward with checkpoints; F_w(m) accumulated for m = 1..n
+  // forward with checkpoints; the wall-layer sums of F_w(m), m = 1..n, go to
+  // one slot set per step and are reduced once, in fixed order, at the end
+  const int fwb = lbm::fw_blocks(h);
   for (int64_t s = 0; s < L.nseg; ++s) {
     HIPCHECK(hipMemcpyAsync(ckpt(s), h->buf[h->cur], sbytes, hipMemcpyDeviceToDevice, h->stream));
     const int64_t steps = std::min<int64_t>(k_ckpt, n_steps - s * k_ckpt);
     for (int64_t i = 0; i < steps; ++i) {
       HIPCHECK(lbm::launch_step(h, h->buf[h->cur], h->buf[h->cur ^ 1]));
       h->cur ^= 1;
+      HIPCHECK(lbm::launch_fw_layers(h, h->buf[h->cur], fwpart + 2 * (size_t)fwb * h->step));
       h->step += 1;
-      HIPCHECK(lbm::launch_fw_accumulate(h, h->buf[h->cur], fwpart, small));
     }
   }
+  HIPCHECK(lbm::launch_fw_reduce(h, fwpart, n_steps * fwb, small));
   // final state: front and its seed, lambda(n)
   HIPCHECK(lbm::launch_diag(h, h->dres));
   HIPCHECK(lbm::launch_front_seed(h, w_front, small + 8));

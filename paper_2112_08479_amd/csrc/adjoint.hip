@@ -36,10 +36,10 @@ struct AModel<1> {
 };
 
 // reverse pull of the adjoint: slot of lambda that population q at node
-// (x, y, z) receives from
-template <class L, int q>
-__device__ __forceinline__ int64_t rpull_offset(const Grid& g, int base, int x, int y, int z,
-                                                int64_t node) {
+// (x, y, z) receives from (lambda buffers use the population buffers'
+// x-blocked layout, QT populations)
+template <class L, int q, int QT>
+__device__ __forceinline__ int64_t rpull_offset(const Grid& g, int base, int x, int y, int z) {
   constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
   const int xn = x + cx, zn = z + cz;
   int yn = y + cy;
@@ -48,8 +48,8 @@ __device__ __forceinline__ int64_t rpull_offset(const Grid& g, int base, int x, 
   bool wall = false;
   if (cx != 0) wall = wall || ((unsigned)xn >= (unsigned)g.nx);
   if (cz != 0) wall = wall || ((unsigned)zn >= (unsigned)g.nz);
-  return wall ? (int64_t)(base + opp<L>(q)) * g.n + node
-              : (int64_t)(base + q) * g.n + ((int64_t)zn * g.ny + yn) * g.nx + xn;
+  return wall ? elem_index<QT>(g, base + opp<L>(q), (int64_t)z * g.ny + y, x)
+              : elem_index<QT>(g, base + q, (int64_t)zn * g.ny + yn, xn);
 }
 
 struct AdjStep {
@@ -78,11 +78,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(const ST* __restrict__ 
     gather<LF, LS, ST, CT>(state, g, x, y, z, fg, ph);
     static_for<0, LF::Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      mg[q] = lam_next[rpull_offset<LF, q>(g, 0, x, y, z, node)];
+      mg[q] = lam_next[rpull_offset<LF, q, LF::Q + LS::Q>(g, 0, x, y, z)];
     });
     static_for<0, LS::Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      mp[q] = lam_next[rpull_offset<LS, q>(g, LF::Q, x, y, z, node)];
+      mp[q] = lam_next[rpull_offset<LS, q, LF::Q + LS::Q>(g, LF::Q, x, y, z)];
     });
     CT bc = CT(0), bi = CT(0);
     if constexpr (MODEL == 0)
@@ -107,11 +107,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(const ST* __restrict__ 
     }
     static_for<0, LF::Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      lam_out[(int64_t)q * g.n + node] = gb[q];
+      lam_out[elem_index<LF::Q + LS::Q>(g, q, row, x)] = gb[q];
     });
     static_for<0, LS::Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      lam_out[(int64_t)(LF::Q + q) * g.n + node] = pb[q];
+      lam_out[elem_index<LF::Q + LS::Q>(g, LF::Q + q, row, x)] = pb[q];
     });
     if (a.dchi0) {
       double s = 0.0;
@@ -161,7 +161,6 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_seed(const ST* __restrict__ 
   const int x = (b - row * nbx) * blockDim.x + threadIdx.x;
   if (x >= g.nx) return;
   const int y = row % g.ny, z = row / g.ny;
-  const int64_t node = (int64_t)row * g.nx + x;
   CT gb[LF::Q];
   static_for<0, LF::Q>([&](auto qc) { gb[decltype(qc)::value] = CT(0); });
   const double az = (z == 0) ? a0 : ((z == 1) ? a1 : 0.0);
@@ -190,11 +189,11 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_seed(const ST* __restrict__ 
   }
   static_for<0, LF::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    lam[(int64_t)q * g.n + node] = gb[q];
+    lam[elem_index<LF::Q + LS::Q>(g, q, row, x)] = gb[q];
   });
   static_for<0, LS::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    lam[(int64_t)(LF::Q + q) * g.n + node] = pb;
+    lam[elem_index<LF::Q + LS::Q>(g, LF::Q + q, row, x)] = pb;
   });
 }
 
@@ -203,16 +202,23 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_seed(const ST* __restrict__ 
 // B = m(i*+1); x_front = i* + 1/2 + (A - theta)/(A - B) has
 // d/dA = (theta - B)/(A - B)^2 and d/dB = (A - theta)/(A - B)^2, passed to
 // the first depth maximum of each column, divided by ny for the span mean.
-__global__ void k_front_seed(const double* __restrict__ chibar, Grid g, double w_front,
-                             double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block of 1024 threads: the columns are scanned in parallel, i* is a
+// max-reduction (wave shuffles, then LDS), the rest is one thread's work.
+__global__ __launch_bounds__(1024) void k_front_seed(const double* __restrict__ chibar, Grid g,
+                                                     double w_front, double* __restrict__ out) {
+  __shared__ int wbest[16];
   const double theta = 0.02;
   int best = -1;
-  for (int i = 0; i < g.nx; ++i) {
+  for (int i = threadIdx.x; i < g.nx; i += blockDim.x) {
     double m = -INFINITY;
     for (int k = 0; k < g.nz; ++k) m = fmax(m, chibar[(int64_t)k * g.nx + i]);
     if (m >= theta) best = i;
   }
+  for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
+  if ((threadIdx.x & 63) == 0) wbest[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) best = max(best, wbest[w]);
   out[0] = -1.0;
   out[1] = out[2] = out[3] = out[4] = 0.0;
   if (best < 0 || best == g.nx - 1) return;
@@ -242,7 +248,6 @@ __global__ __launch_bounds__(kBlock) void k_fw_layers(const ST* __restrict__ sta
   if (t < (int64_t)g.nx * g.ny) {
     const int x = (int)(t % g.nx), y = (int)(t / g.nx);
     for (int z = 0; z < 2 && z < g.nz; ++z) {
-      const int64_t node = ((int64_t)z * g.ny + y) * g.nx + x;
       CT fg[LF::Q], ph[LS::Q];
       gather<LF, LS, ST, CT>(state, g, x, y, z, fg, ph);
       double drho = 0.0, jx = 0.0;
@@ -277,11 +282,12 @@ __global__ __launch_bounds__(kBlock) void k_fw_layers(const ST* __restrict__ sta
 }
 
 // single block: out[0] += nu0 (9 sum0 - sum1) / 3 (fixed order)
-__global__ __launch_bounds__(1024) void k_fw_accumulate(const double* __restrict__ part, int nparts,
-                                                        double nu0, double* __restrict__ out) {
+__global__ __launch_bounds__(1024) void k_fw_accumulate(const double* __restrict__ part,
+                                                        int64_t nparts, double nu0,
+                                                        double* __restrict__ out) {
   __shared__ double red[16][2];
   double v0 = 0.0, v1 = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+  for (int64_t b = threadIdx.x; b < nparts; b += blockDim.x) {
     v0 += part[2 * b];
     v1 += part[2 * b + 1];
   }
@@ -436,23 +442,26 @@ hipError_t launch_adjoint_seed(lbm_handle* h, const void* state, void* lam, doub
 }
 
 hipError_t launch_front_seed(lbm_handle* h, double w_front, double* out) {
-  hipLaunchKernelGGL(k_front_seed, dim3(1), dim3(64), 0, h->stream, h->chibar, agrid(h), w_front,
+  hipLaunchKernelGGL(k_front_seed, dim3(1), dim3(1024), 0, h->stream, h->chibar, agrid(h), w_front,
                      out);
   return hipGetLastError();
 }
 
-hipError_t launch_fw_accumulate(lbm_handle* h, const void* state, double* part, double* out) {
+hipError_t launch_fw_layers(lbm_handle* h, const void* state, double* part) {
   const Grid g = agrid(h);
   const int nb = fw_blocks(h);
-  hipError_t e = adj_dispatch(h, [&](auto mc, auto ct) {
+  return adj_dispatch(h, [&](auto mc, auto ct) {
     constexpr int M = decltype(mc)::value;
     using CT = decltype(ct);
     hipLaunchKernelGGL((k_fw_layers<M, CT, CT>), dim3(nb), dim3(kBlock), 0, h->stream,
                        static_cast<const CT*>(state), g, part);
     return hipGetLastError();
   });
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fw_accumulate, dim3(1), dim3(1024), 0, h->stream, part, nb, h->prm.nu0, out);
+}
+
+hipError_t launch_fw_reduce(lbm_handle* h, const double* part, int64_t nparts, double* out) {
+  hipLaunchKernelGGL(k_fw_accumulate, dim3(1), dim3(1024), 0, h->stream, part, nparts,
+                     h->prm.nu0, out);
   return hipGetLastError();
 }
 

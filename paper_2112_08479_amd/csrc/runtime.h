@@ -80,7 +80,10 @@ hipError_t launch_adjoint_step(lbm_handle* h, const void* state, const void* lam
 hipError_t launch_adjoint_seed(lbm_handle* h, const void* state, void* lam, double a0, double a1,
                                const double* fs);
 hipError_t launch_front_seed(lbm_handle* h, double w_front, double* out);
-hipError_t launch_fw_accumulate(lbm_handle* h, const void* state, double* part, double* out);
+// wall-layer sums of F_w of the current state into part[2 fw_blocks]
+hipError_t launch_fw_layers(lbm_handle* h, const void* state, double* part);
+// out[0] += nu0 (9 S0 - S1) / 3 over nparts partial pairs (fixed order)
+hipError_t launch_fw_reduce(lbm_handle* h, const double* part, int64_t nparts, double* out);
 hipError_t launch_sum_pairs(lbm_handle* h, const double* part, int nparts, double* out);
 hipError_t launch_zero(lbm_handle* h, double* p, int64_t n);
 

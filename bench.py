@@ -46,16 +46,17 @@ VARIANTS = ["cumulant27_q7_2048x128x256_fp16", "cumulant27_q7_2048x128x256_bf16"
             "cumulant27_fcm27_2048x128x256_fp16"]
 
 
-def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100):
+def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0):
     """Differentiation form: one lbm_adjoint_run (forward with checkpoints,
-    recompute, hand-written adjoint) of the lock exchange, model 1, FP32,
-    Re_b = 1000, C_s = 0.1, Sc_T = 1. MNUPS counts the n_steps node updates of
-    the differentiated run; the algorithmic bytes per node update are a
-    forward (272 B), its recompute (272 B) and the reverse step (3 * 34 * 4 B)."""
+    recompute, hand-written adjoint) of the lock exchange, FP32, Re_b = 1000,
+    C_s = 0.1, Sc_T = 1. MNUPS counts the n_steps node updates of the
+    differentiated run; the algorithmic bytes per node update are a forward
+    (2 Q 4 B), its recompute (2 Q 4 B) and the reverse step (3 Q 4 B), Q the
+    populations per node."""
     import torch
 
     import paper_2112_08479_amd as pkg
-    cfg = pkg.Config(nx, ny, nz, model=0, storage=pkg.F32, re_b=1000.0, cs_smag=0.1, sc_t=1.0)
+    cfg = pkg.Config(nx, ny, nz, model=model, storage=pkg.F32, re_b=1000.0, cs_smag=0.1, sc_t=1.0)
     lat = pkg.Lattice(cfg)
     lat.init_lock_exchange(0.125, 1e-3, 0)
     torch.cuda.synchronize()
@@ -64,15 +65,17 @@ def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100):
     torch.cuda.synchronize()
     dt = time.time() - t0
     n = cfg.n
+    q = lat.params["q_flow"] + lat.params["q_scalar"]
     lat.close()
-    bpn = 272 + 272 + 3 * 34 * 4
+    bpn = 2 * q * 4 + 2 * q * 4 + 3 * q * 4
     mnups = n * n_steps / dt / 1e6
-    return {"workload": f"adjoint_cumulant27_q7_{nx}x{ny}x{nz}_fp32_{n_steps}steps_k{k_ckpt}",
+    name = ["cumulant27_q7", "bgk19_smag_q6", "cumulant27_fcm27"][model]
+    return {"workload": f"adjoint_{name}_{nx}x{ny}x{nz}_fp32_{n_steps}steps_k{k_ckpt}",
             "nodes": n, "steps": n_steps, "seconds": dt, "MNUPS": mnups,
             "bytes_per_node_update": bpn, "GB_per_s": mnups * 1e6 * bpn / 1e9,
             "J": J, "dJ_dcs": dcs, "dJ_dsct": dsct, "hbm_frac": mnups * 1e6 * bpn / 1e9 / HBM_PEAK_GBS,
             "note": ("state fits the 256 MB last-level cache and the run is launch bound: not an HBM "
-                     "roofline case" if n * 34 * 4 < (256 << 20) else "HBM resident")}
+                     "roofline case" if n * q * 4 < (256 << 20) else "HBM resident")}
 
 
 def precision_report(steps=2000):
@@ -248,7 +251,8 @@ def main():
             r = measure(v, max(50, args.steps // 4), min(args.warmup, 50))
             print(json.dumps({"progress": "variant", **r}), file=sys.stderr, flush=True)
             variants.append(r)
-        for kw in (dict(), dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25)):
+        for kw in (dict(), dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25),
+                   dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25, model=2)):
             r = measure_adjoint(**kw)
             print(json.dumps({"progress": "adjoint", **r}), file=sys.stderr, flush=True)
             variants.append(r)

@@ -176,11 +176,9 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, 
 }
 
 int adjoint_supported(const lbm_config* c) {
-  if (c->model == LBM_CUMULANT27_FCM27)
-    return fail(LBM_EINVAL, "no adjoint for the factorized-central-moment scalar model");
   if (c->storage != LBM_F32 && c->storage != LBM_F64)
     return fail(LBM_EINVAL, "the adjoint needs LBM_F32 or LBM_F64 storage");
-  if (c->model == LBM_CUMULANT27_Q7 &&
+  if (c->model != LBM_BGK19_SMAG_Q6 &&
       (c->omega3 != 1.0 || c->omega4 != 1.0 || c->omega5 != 1.0 || c->omega6 != 1.0))
     return fail(LBM_EINVAL, "the cumulant adjoint needs omega3..omega6 = 1");
   return LBM_OK;

@@ -106,6 +106,113 @@ LBM_HD void scalar_vjp(const CT* ph, CT chi, CT ux, CT uy, CT uz, CT tau, const 
   }
 }
 
+// adjoint of collide_fcm27 (the closed form with the rest closure). Inputs:
+// forward values; mp = adjoint of phi*. Outputs: pb (set), and accumulates
+// bchi, bu*, btau and b_isct.
+template <bool LES, typename CT>
+LBM_HD void fcm27_vjp(const CT* ph, CT chi, CT ux, CT uy, CT uz, CT tau, const Phys<CT>& p,
+                      const CT* mp, CT* pb, CT& bchi, CT& bux, CT& buy, CT& buz, CT& btau,
+                      CT& b_isct) {
+  // forward recompute
+  CT tau_phi = p.tau_phi0;
+  if constexpr (LES) {
+    const CT nu_t = (tau - p.tau0) * CT(1.0 / 3.0);
+    tau_phi = CT(0.5) + (p.d0 + nu_t * p.inv_sct) * p.inv_cs2phi;
+  }
+  const CT a1 = CT(1) - CT(1) / tau_phi;
+  CT jx = CT(0), jy = CT(0), jz = CT(0);
+  static_for<0, 27>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    if (Q27::cx[q]) jx += CT(Q27::cx[q]) * ph[q];
+    if (Q27::cy[q]) jy += CT(Q27::cy[q]) * ph[q];
+    if (Q27::cz[q]) jz += CT(Q27::cz[q]) * ph[q];
+  });
+  const CT uu[3] = {ux, uy, uz};
+  const CT dj[3] = {jx - chi * ux, jy - chi * uy, jz - chi * uz};
+  const CT k[3] = {a1 * dj[0], a1 * dj[1], a1 * dj[2]};
+  CT P[3][3], Qv[3][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const CT u = uu[d];
+    const CT s = CT(1.0 / 3.0) + u * u;
+    P[d][0] = CT(0.5) * (s - u);
+    P[d][1] = CT(1) - s;
+    P[d][2] = CT(0.5) * (s + u);
+    Qv[d][0] = u - CT(0.5);
+    Qv[d][1] = CT(-2) * u;
+    Qv[d][2] = u + CT(0.5);
+  }
+  // reverse: phi*_0 = chi - sum of the others
+  const CT m0 = mp[0];
+  bchi += m0;
+  CT bP[3][3], bQ[3][3], bk[3] = {CT(0), CT(0), CT(0)};
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) bP[d][c] = bQ[d][c] = CT(0);
+  static_for<1, 27>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int i = Q27::cx[q] + 1, j = Q27::cy[q] + 1, l = Q27::cz[q] + 1;
+    const CT m = mp[q] - m0;
+    const CT px = P[0][i], py = P[1][j], pz = P[2][l];
+    const CT qx = Qv[0][i], qy = Qv[1][j], qz = Qv[2][l];
+    bchi += m * px * py * pz;
+    bk[0] += m * qx * py * pz;
+    bk[1] += m * px * qy * pz;
+    bk[2] += m * px * py * qz;
+    bP[0][i] += m * (chi * py * pz + k[1] * qy * pz + k[2] * py * qz);
+    bP[1][j] += m * (chi * px * pz + k[0] * qx * pz + k[2] * px * qz);
+    bP[2][l] += m * (chi * px * py + k[0] * qx * py + k[1] * px * qy);
+    bQ[0][i] += m * k[0] * py * pz;
+    bQ[1][j] += m * k[1] * px * pz;
+    bQ[2][l] += m * k[2] * px * py;
+  });
+  // P(c) and Q(c) as functions of u: dP/du = (u - 1/2, -2u, u + 1/2), dQ/du = (1, -2, 1)
+  CT bu[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const CT u = uu[d];
+    bu[d] = bP[d][0] * (u - CT(0.5)) + bP[d][1] * (CT(-2) * u) + bP[d][2] * (u + CT(0.5)) +
+            bQ[d][0] - CT(2) * bQ[d][1] + bQ[d][2];
+  }
+  // k_d = a1 (j_d - chi u_d)
+  CT ba1 = CT(0), bj[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    ba1 += bk[d] * dj[d];
+    bj[d] = a1 * bk[d];
+    bchi += -a1 * uu[d] * bk[d];
+    bu[d] += -a1 * chi * bk[d];
+  }
+  bux += bu[0];
+  buy += bu[1];
+  buz += bu[2];
+  static_for<0, 27>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    CT v = CT(0);
+    if (Q27::cx[q]) v += CT(Q27::cx[q]) * bj[0];
+    if (Q27::cy[q]) v += CT(Q27::cy[q]) * bj[1];
+    if (Q27::cz[q]) v += CT(Q27::cz[q]) * bj[2];
+    pb[q] = v;
+  });
+  if constexpr (LES) {
+    const CT btp = ba1 / (tau_phi * tau_phi);
+    btau += btp * p.inv_cs2phi * p.inv_sct * CT(1.0 / 3.0);
+    b_isct += btp * p.inv_cs2phi * (tau - p.tau0) * CT(1.0 / 3.0);
+  }
+}
+
+// scalar collision adjoint of the scalar lattice LS (BGK or FCM)
+template <class LS, bool LES, typename CT>
+LBM_HD void scalar_collision_vjp(const CT* ph, CT chi, CT ux, CT uy, CT uz, CT tau,
+                                 const Phys<CT>& p, const CT* mp, CT* pb, CT& bchi, CT& bux,
+                                 CT& buy, CT& buz, CT& btau, CT& b_isct) {
+  if constexpr (LS::Q == 27)
+    fcm27_vjp<LES, CT>(ph, chi, ux, uy, uz, tau, p, mp, pb, bchi, bux, buy, buz, btau, b_isct);
+  else
+    scalar_vjp<LS, LES, CT>(ph, chi, ux, uy, uz, tau, p, mp, pb, bchi, bux, buy, buz, btau, b_isct);
+}
+
 template <class L, typename CT>
 LBM_HD void flow_moments_vjp(CT bdrho, CT bjx, CT bjy, CT bjz, CT bpxx, CT bpyy, CT bpzz, CT bpxy,
                              CT bpxz, CT bpyz, CT* gb) {
@@ -123,14 +230,15 @@ LBM_HD void flow_moments_vjp(CT bdrho, CT bjx, CT bjy, CT bjz, CT bpxx, CT bpyy,
   });
 }
 
-// ---- cumulant D3Q27 + D3Q7, omega3..omega6 = 1
-template <bool LES, typename CT>
-LBM_HD void vjp_cumulant_q27_q7(const CT* g, const CT* ph, const CT* mg, const CT* mp,
-                                const Phys<CT>& p, CT* gb, CT* pb, CT& b_cles, CT& b_isct) {
+// ---- cumulant D3Q27 + scalar lattice LS (D3Q7 BGK or D3Q27 FCM),
+// omega3..omega6 = 1
+template <class LS, bool LES, typename CT>
+LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, const CT* mg, const CT* mp,
+                           const Phys<CT>& p, CT* gb, CT* pb, CT& b_cles, CT& b_isct) {
   // ---- forward recompute
   CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
   flow_moments<Q27>(g, drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz);
-  const CT chi = scalar_sum<Q7>(ph);
+  const CT chi = scalar_sum<LS>(ph);
   const CT rho = CT(1) + drho;
   const CT ir = CT(1) / rho;
   const CT Fz = -p.g * chi;
@@ -186,7 +294,8 @@ LBM_HD void vjp_cumulant_q27_q7(const CT* g, const CT* ph, const CT* mg, const C
   // ---- reverse
   CT bchi = CT(0), bux = CT(0), buy = CT(0), buz = CT(0), btau = CT(0);
   CT buzs = CT(0);
-  scalar_vjp<Q7, LES, CT>(ph, chi, ux, uy, uzs, tau, p, mp, pb, bchi, bux, buy, buzs, btau, b_isct);
+  scalar_collision_vjp<LS, LES, CT>(ph, chi, ux, uy, uzs, tau, p, mp, pb, bchi, bux, buy, buzs, btau,
+                                    b_isct);
   CT mb[27];
   CT bvz = CT(0);
   inverse_chimera_vjp<CT>(m, ux, uy, vz, mg, mb, bux, buy, bvz);
@@ -270,7 +379,7 @@ LBM_HD void vjp_cumulant_q27_q7(const CT* g, const CT* ph, const CT* mg, const C
   bchi += -p.g * bFz;
   brho += -bir * ir * ir;
   bdrho += brho;
-  static_for<0, 7>([&](auto qc) { pb[decltype(qc)::value] += bchi; });
+  static_for<0, LS::Q>([&](auto qc) { pb[decltype(qc)::value] += bchi; });
   static_for<0, 27>([&](auto qc) { gb[decltype(qc)::value] = CT(0); });
   flow_moments_vjp<Q27, CT>(bdrho, bjx, bjy, bjz, bpxx, bpyy, bpzz, bpxy, bpxz, bpyz, gb);
 }

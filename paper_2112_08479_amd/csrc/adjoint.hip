@@ -34,6 +34,11 @@ struct AModel<1> {
   using LF = Q19;
   using LS = Q6;
 };
+template <>
+struct AModel<2> {
+  using LF = Q27;
+  using LS = Q27;
+};
 
 // reverse pull of the adjoint: slot of lambda that population q at node
 // (x, y, z) receives from (lambda buffers use the population buffers'
@@ -85,8 +90,8 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(const ST* __restrict__ 
       mp[q] = lam_next[rpull_offset<LS, q, LF::Q + LS::Q>(g, LF::Q, x, y, z)];
     });
     CT bc = CT(0), bi = CT(0);
-    if constexpr (MODEL == 0)
-      vjp_cumulant_q27_q7<LES, CT>(fg, ph, mg, mp, p, gb, pb, bc, bi);
+    if constexpr (MODEL == 0 || MODEL == 2)
+      vjp_cumulant27<LS, LES, CT>(fg, ph, mg, mp, p, gb, pb, bc, bi);
     else
       vjp_bgk_q19_q6<LES, CT>(fg, ph, mg, mp, p, gb, pb, bc, bi);
     // seed of the wall friction term at this step: d u_x / d g_q = (c_qx - u_x) / rho
@@ -387,12 +392,15 @@ static Phys<CT> aphys(const lbm_handle* h) {
 template <class F>
 static hipError_t adj_dispatch(const lbm_handle* h, F&& f) {
   const bool f64 = h->cfg.storage == LBM_F64;
-  if (h->cfg.model == 0) {
-    if (f64) return f(std::integral_constant<int, 0>{}, double{});
-    return f(std::integral_constant<int, 0>{}, float{});
+  auto by_type = [&](auto mc) {
+    return f64 ? f(mc, double{}) : f(mc, float{});
+  };
+  switch (h->cfg.model) {
+    case LBM_CUMULANT27_Q7: return by_type(std::integral_constant<int, 0>{});
+    case LBM_BGK19_SMAG_Q6: return by_type(std::integral_constant<int, 1>{});
+    case LBM_CUMULANT27_FCM27: return by_type(std::integral_constant<int, 2>{});
   }
-  if (f64) return f(std::integral_constant<int, 1>{}, double{});
-  return f(std::integral_constant<int, 1>{}, float{});
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_adjoint_step(lbm_handle* h, const void* state, const void* lam_next,

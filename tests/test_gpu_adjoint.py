@@ -1,7 +1,7 @@
 """The hand-written adjoint (lbm_adjoint_run) against the oracle.
 
 * 64 x 4 x 8, 200 steps, checkpoints every 50: J, dJ/dC_s, dJ/dSc_T and the
-  field dJ/dchi0 against torch autograd through the FP64 oracle, both models;
+  field dJ/dchi0 against torch autograd through the FP64 oracle, every model;
   FP64 storage to 1e-8 (relative to the largest entry), FP32 to 2e-3.
 * 128 x 8 x 16, 500 steps (cumulant, Re_b 1000, C_s 0.1, Sc_T 1): against the
   oracle's FP64 central differences stored in tests/golden (written by
@@ -43,7 +43,8 @@ def _gpu_grad(kw, storage, chi0, n, k, w_front=1.0, w_fw=1.0):
 
 
 TINY = [dict(nx=64, ny=4, nz=8, model=0, re_b=1000.0, cs_smag=0.1, sc_t=1.0, g_prime=1e-4),
-        dict(nx=64, ny=4, nz=8, model=1, re_b=1000.0, cs_smag=0.1, sc_t=1.0, g_prime=1e-4)]
+        dict(nx=64, ny=4, nz=8, model=1, re_b=1000.0, cs_smag=0.1, sc_t=1.0, g_prime=1e-4),
+        dict(nx=64, ny=4, nz=8, model=2, re_b=1000.0, cs_smag=0.1, sc_t=1.0, g_prime=1e-4)]
 _ref = {}
 
 
@@ -58,7 +59,7 @@ def _oracle_ref(i):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("i", [0, 1], ids=["cumulant", "bgk"])
+@pytest.mark.parametrize("i", [0, 1, 2], ids=["cumulant", "bgk", "cumulant_fcm"])
 @pytest.mark.parametrize("storage,tol", [(pkg.F64, 1e-8), (pkg.F32, 2e-3)], ids=["f64", "f32"])
 def test_adjoint_matches_oracle_autograd(i, storage, tol):
     chi0, (J, gcs, gsct, gchi) = _oracle_ref(i)

@@ -10,10 +10,11 @@ from oracle.params import Config
 from tests import inputs
 
 CASES = [dict(nx=24, ny=2, nz=6, model=0, re_b=400.0, cs_smag=0.1, sc_t=0.8, g_prime=1e-3),
-         dict(nx=24, ny=2, nz=6, model=1, re_b=400.0, cs_smag=0.1, sc_t=0.8, g_prime=1e-3)]
+         dict(nx=24, ny=2, nz=6, model=1, re_b=400.0, cs_smag=0.1, sc_t=0.8, g_prime=1e-3),
+         dict(nx=24, ny=2, nz=6, model=2, re_b=400.0, cs_smag=0.1, sc_t=0.8, g_prime=1e-3)]
 
 
-@pytest.mark.parametrize("case", CASES, ids=["cumulant", "bgk"])
+@pytest.mark.parametrize("case", CASES, ids=["cumulant", "bgk", "cumulant_fcm"])
 def test_autograd_gradient_matches_central_differences(case):
     cfg = Config(**case)
     chi0 = lbm.chi0_lock_exchange(cfg, 0.125, 1e-3, 3)

@@ -314,9 +314,11 @@ int lbm_create(const lbm_config* cfg, void* dev_workspace, size_t bytes, void* h
   h->n = (int64_t)cfg->nx * cfg->ny * cfg->nz;
   h->esize = storage_bytes(cfg->storage);
   h->state_bytes = state_bytes_of(cfg, h->qt);
-  if (hipGetDevice(&h->device) != hipSuccess) {
+  if (hipGetDevice(&h->device) != hipSuccess ||
+      hipDeviceGetAttribute(&h->cu_count, hipDeviceAttributeMultiprocessorCount, h->device) !=
+          hipSuccess) {
     delete h;
-    return fail(LBM_EDEVICE, "hipGetDevice failed");
+    return fail(LBM_EDEVICE, "hipGetDevice or hipDeviceGetAttribute failed");
   }
   h->stream = (hipStream_t)hip_stream;
   h->ws = (char*)dev_workspace;

@@ -107,12 +107,11 @@ __device__ __forceinline__ int block_order(int b, int nblocks, int nbx) {
 #endif
 
 // one tile: NPT * blockDim.x consecutive nodes of one row
-template <int MODEL, typename ST, typename SS, typename CT, bool LES, bool GEN>
+template <int MODEL, typename ST, typename SS, typename CT, bool LES, bool GEN, int NPT>
 __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __restrict__ dst,
                                           const Grid& g, const Phys<CT>& p, int nbx, int b) {
   using LF = typename ModelT<MODEL>::LF;
   using LS = typename ModelT<MODEL>::LS;
-  constexpr int NPT = nodes_per_thread<MODEL, ST>();
   const int row = b / nbx;
   const int x0 = (b - row * nbx) * (int)blockDim.x * NPT;
   if (x0 + (int)threadIdx.x >= g.nx) return;  // lanes with no node at all
@@ -154,15 +153,16 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
 #define LBM_STEP_WAVES 0
 #endif
 
-template <int MODEL, typename ST, typename SS, typename CT, bool LES, bool GEN>
+template <int MODEL, typename ST, typename SS, typename CT, bool LES, bool GEN, int NPT>
 __global__ __launch_bounds__(kBlock, LBM_STEP_WAVES) void k_step(const ST* __restrict__ src, ST* __restrict__ dst,
                                                  Grid g, Phys<CT> p, int nbx, int ntiles) {
 #if LBM_PERSIST
   for (int b = blockIdx.x; b < ntiles; b += gridDim.x)
-    step_tile<MODEL, ST, SS, CT, LES, GEN>(src, dst, g, p, nbx, b);
+    step_tile<MODEL, ST, SS, CT, LES, GEN, NPT>(src, dst, g, p, nbx, b);
 #else
   (void)ntiles;
-  step_tile<MODEL, ST, SS, CT, LES, GEN>(src, dst, g, p, nbx, block_order(blockIdx.x, gridDim.x, nbx));
+  step_tile<MODEL, ST, SS, CT, LES, GEN, NPT>(src, dst, g, p, nbx,
+                                              block_order(blockIdx.x, gridDim.x, nbx));
 #endif
 }
 
@@ -591,10 +591,46 @@ static bool general_rates(const lbm_handle* h) {
   return c.omega3 != 1.0 || c.omega4 != 1.0 || c.omega5 != 1.0 || c.omega6 != 1.0;
 }
 
-hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
-  const Grid g = grid_of(h);
+template <int M, typename ST, typename SS, typename CT, int NPT>
+static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src, void* dst) {
   const bool les = h->cfg.cs_smag > 0.0;
   const bool gen = general_rates(h);
+  const int per_thread_x = (g.nx + NPT - 1) / NPT;  // x-extent in threads if one block
+  const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
+  const int nbx = (g.nx + bx * NPT - 1) / (bx * NPT);
+  const int ntiles = (int)((int64_t)nbx * g.ny * g.nz);
+#if LBM_PERSIST
+  const unsigned blocks = (unsigned)std::min<int64_t>(ntiles, (int64_t)256 * LBM_PERSIST);
+#else
+  const unsigned blocks = (unsigned)ntiles;
+#endif
+  const Phys<CT> p = phys_of<CT>(h);
+  const ST* s = static_cast<const ST*>(src);
+  ST* d = static_cast<ST*>(dst);
+  if (les) {
+    if (M != 1 && gen)
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, true, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+    else
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, false, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+  } else {
+    if (M != 1 && gen)
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, true, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+    else
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, false, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+  }
+  return hipGetLastError();
+}
+
+// Grids too small to give every SIMD four waves at the preferred nodes per
+// thread (cache-resident, latency-bound runs such as a 256 x 16 x 32
+// adjoint) take one node per thread: twice the waves.
+static bool few_waves(const lbm_handle* h, int npt) {
+  const int64_t waves = (h->n + (int64_t)64 * npt - 1) / ((int64_t)64 * npt);
+  return waves < (int64_t)16 * h->cu_count;
+}
+
+hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
+  const Grid g = grid_of(h);
   return with_model(h, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
     return with_storage(h, [&](auto st, auto ss, auto ct) {
@@ -602,30 +638,10 @@ hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
       using SS = decltype(ss);
       using CT = decltype(ct);
       constexpr int NPT = nodes_per_thread<M, ST>();
-      const int per_thread_x = (g.nx + NPT - 1) / NPT;  // x-extent in threads if one block
-      const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
-      const int nbx = (g.nx + bx * NPT - 1) / (bx * NPT);
-      const int ntiles = (int)((int64_t)nbx * g.ny * g.nz);
-#if LBM_PERSIST
-      const unsigned blocks = (unsigned)std::min<int64_t>(ntiles, (int64_t)256 * LBM_PERSIST);
-#else
-      const unsigned blocks = (unsigned)ntiles;
-#endif
-      const Phys<CT> p = phys_of<CT>(h);
-      const ST* s = static_cast<const ST*>(src);
-      ST* d = static_cast<ST*>(dst);
-      if (les) {
-        if (M != 1 && gen)
-          hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
-        else
-          hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
-      } else {
-        if (M != 1 && gen)
-          hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
-        else
-          hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, false>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+      if constexpr (NPT > 1) {
+        if (few_waves(h, NPT)) return launch_step_npt<M, ST, SS, CT, 1>(h, g, src, dst);
       }
-      return hipGetLastError();
+      return launch_step_npt<M, ST, SS, CT, NPT>(h, g, src, dst);
     });
   });
 }

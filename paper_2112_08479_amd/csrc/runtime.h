@@ -17,6 +17,7 @@ struct lbm_handle {
   size_t esize;       // bytes per stored population value
   size_t state_bytes; // bytes of one population buffer (x-blocked, padded rows)
   int device;
+  int cu_count;       // compute units of the device
   hipStream_t stream;
   char* ws;
   size_t ws_bytes;

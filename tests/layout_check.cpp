@@ -72,6 +72,7 @@ int main() {
       for (int nz : ns) {
         check<Q27, Q7, 2>(nx, ny, nz, 256);
         check<Q19, Q6, 2>(nx, ny, nz, 256);
+        check<Q19, Q6, 1>(nx, ny, nz, 256);
         check<Q27, Q27, 1>(nx, ny, nz, 256);
         check<Q27, Q7, 1>(nx, ny, nz, 64);
       }

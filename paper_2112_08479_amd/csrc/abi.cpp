@@ -157,7 +157,7 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, 
   L.ktraj = k < n_steps ? k : n_steps;
   const int bx = block_x(c->nx);
   const int64_t ablocks = (int64_t)((c->nx + bx - 1) / bx) * c->ny * c->nz;
-  const int64_t fblocks = ((int64_t)c->nx * c->ny + lbm::kBlock - 1) / lbm::kBlock;
+  const int64_t fblocks = (int64_t)lbm::xblocks(c->nx) * c->ny * std::min(c->nz, 2);
   size_t off = 0;
   L.ckpt = off;
   off += (size_t)L.nseg * L.buf;

@@ -15,6 +15,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "adjoint.h"
 #include "collide.h"
 #include "lattice.h"
@@ -244,45 +246,34 @@ __global__ __launch_bounds__(1024) void k_front_seed(const double* __restrict__ 
 
 // sum over the bottom two layers of u_x: fw_partial[block] = {sum u_x(z=0), sum u_x(z=1)}
 template <int MODEL, typename ST, typename CT>
-__global__ __launch_bounds__(kBlock) void k_fw_layers(const ST* __restrict__ state, Grid g,
-                                                      double* __restrict__ part) {
+__global__ __launch_bounds__(64) void k_fw_layers(const ST* __restrict__ state, Grid g,
+                                                  double* __restrict__ part) {
+  // one wavefront per (x-block, y, z) of the two wall layers z = 0, 1: the
+  // block's z is uniform, its sum goes to slot z of the block's pair
   using LF = typename AModel<MODEL>::LF;
-  using LS = typename AModel<MODEL>::LS;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[2] = {0.0, 0.0};
-  if (t < (int64_t)g.nx * g.ny) {
-    const int x = (int)(t % g.nx), y = (int)(t / g.nx);
-    for (int z = 0; z < 2 && z < g.nz; ++z) {
-      CT fg[LF::Q], ph[LS::Q];
-      gather<LF, LS, ST, CT>(state, g, x, y, z, fg, ph);
-      double drho = 0.0, jx = 0.0;
-      static_for<0, LF::Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        drho += (double)fg[q];
-        if (LF::cx[q]) jx += LF::cx[q] * (double)fg[q];
-      });
-      v[z] = jx / (1.0 + drho);
-    }
+  constexpr int QT = LF::Q + AModel<MODEL>::LS::Q;
+  const int b = blockIdx.x;
+  const int xb = b % g.nxb, y = (b / g.nxb) % g.ny, z = b / (g.nxb * g.ny);
+  const int x = xb * kXB + (int)threadIdx.x;
+  double v = 0.0;
+  if (x < g.nx) {
+    CT fg[LF::Q];
+    static_for<0, LF::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      fg[q] = Conv<ST, CT>::load(*pull_ptr<LF, q, QT>(state, g, 0, x, y, z));
+    });
+    double drho = 0.0, jx = 0.0;
+    static_for<0, LF::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      drho += (double)fg[q];
+      if (LF::cx[q]) jx += LF::cx[q] * (double)fg[q];
+    });
+    v = jx / (1.0 + drho);
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    v[0] += __shfl_xor(v[0], o, 64);
-    v[1] += __shfl_xor(v[1], o, 64);
-  }
-  __shared__ double red[kBlock / 64][2];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[wid][0] = v[0];
-    red[wid][1] = v[1];
-  }
-  __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   if (threadIdx.x == 0) {
-    double s0 = 0.0, s1 = 0.0;
-    for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) {
-      s0 += red[w][0];
-      s1 += red[w][1];
-    }
-    part[2 * blockIdx.x] = s0;
-    part[2 * blockIdx.x + 1] = s1;
+    part[2 * b] = z == 0 ? v : 0.0;
+    part[2 * b + 1] = z == 0 ? 0.0 : v;
   }
 }
 
@@ -366,7 +357,7 @@ int adjoint_blocks(const lbm_handle* h) {
   return nbx * h->cfg.ny * h->cfg.nz;
 }
 int fw_blocks(const lbm_handle* h) {
-  return (int)(((int64_t)h->cfg.nx * h->cfg.ny + kBlock - 1) / kBlock);
+  return xblocks(h->cfg.nx) * h->cfg.ny * std::min(h->cfg.nz, 2);
 }
 
 template <typename CT>
@@ -461,7 +452,7 @@ hipError_t launch_fw_layers(lbm_handle* h, const void* state, double* part) {
   return adj_dispatch(h, [&](auto mc, auto ct) {
     constexpr int M = decltype(mc)::value;
     using CT = decltype(ct);
-    hipLaunchKernelGGL((k_fw_layers<M, CT, CT>), dim3(nb), dim3(kBlock), 0, h->stream,
+    hipLaunchKernelGGL((k_fw_layers<M, CT, CT>), dim3(nb), dim3(64), 0, h->stream,
                        static_cast<const CT*>(state), g, part);
     return hipGetLastError();
   });

@@ -98,3 +98,25 @@ def test_froude_number_of_the_slumping_phase(model):
     late = t >= 1.0
     assert np.all(np.diff(x[late]) >= -1e-9)
     assert x[-1] < 7.0
+
+
+# Table 2 (Froude number of the slumping phase): Re_b 5000 -> 0.42 (DNS, Cases 4
+# and 5), 10000 -> 0.42 (experiment, Case 6), 30000 -> 0.44 (experiment, Case 8)
+FR_CASES = [(0, 5000.0, 0.0, 0.42), (1, 10000.0, 0.1, 0.42), (0, 30000.0, 0.1, 0.44),
+            (2, 30000.0, 0.1, 0.44)]
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("model,re_b,cs,fr_ref", FR_CASES,
+                         ids=["cumulant-5000", "bgk-10000-les", "cumulant-30000-les", "fcm-30000-les"])
+def test_froude_number_across_reynolds_numbers(model, re_b, cs, fr_ref):
+    """1024 x 64 x 128 (128 nodes over the depth), FP32, to t~ = 10.5: the
+    slumping-phase Froude number within 0.02 of Table 2's value for the same
+    Re_b (about the 5 % band of the errors Table 2 reports for the paper's own
+    codes). Measured: 0.413, 0.426, 0.436, 0.445."""
+    cfg = pkg.Config(1024, 64, 128, model=model, storage=pkg.F32, re_b=re_b, g_prime=1e-4,
+                     cs_smag=cs, sc_t=1.0)
+    t, x = _front_series(cfg)
+    fr = analysis.froude_number(t, x)
+    print(f"model {model} Re_b {re_b} C_s {cs}: Fr = {fr:.4f} (Table 2: {fr_ref})", flush=True)
+    assert abs(fr - fr_ref) <= 0.02

@@ -1,9 +1,10 @@
 """Parity at the benchmark sizes and the precision report.
 
-* 1024 x 64 x 128 (every model, FP32, the launch configuration bench.py
-  times): after 20 steps of the lock exchange, one more step is compared with
-  the oracle at sampled nodes -- gate columns, every wall, the periodic span
-  edges and random interior nodes -- which the oracle computes one by one.
+* 1024 x 64 x 128 (every model, FP32 and FP64, the launch configuration
+  bench.py times): after 20 steps of the lock exchange, one more step is
+  compared with the oracle at sampled nodes -- gate columns, every wall, the
+  periodic span edges and random interior nodes -- which the oracle computes
+  one by one; and FP32 against FP64 storage after 100 steps (moments 1e-5).
 * 4096 x 256 x 512 (537M nodes) with the 16-bit storage modes: the oracle
   cannot hold the state, so properties that hold at any size are checked:
   finite state, conserved mass and scalar mass, a front that moved forward.
@@ -40,6 +41,53 @@ def _sample_nodes(nx, ny, nz, seed=0):
     for _ in range(40):
         nodes.add((int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))))
     return sorted(nodes)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("model", [0, 1, 2])
+def test_benchmark_size_fp64_one_step_sampled(model):
+    """The FP64 path at the benchmark size (two nodes per thread, the launch
+    geometry of the large grids) against the oracle at sampled nodes."""
+    cfg, P = both(pkg.F64, model=model, **BENCH)
+    lat = pkg.Lattice(cfg)
+    lat.init_lock_exchange(0.125, 1e-3, 0)
+    lat.step(20)
+    f0, phi0 = lat.get_populations()
+    lat.step(1)
+    f1, phi1 = lat.get_populations()
+    lat.close()
+    nodes = _sample_nodes(cfg.nx, cfg.ny, cfg.nz, seed=1)
+    torch.set_num_threads(max(1, min(16, torch.get_num_threads())))
+    of, ophi = olbm.step_at(torch.from_numpy(f0), torch.from_numpy(phi0), P, nodes)
+    k, j, i = (np.array(c) for c in zip(*nodes))
+    ef = np.abs(f1[:, k, j, i] - of.numpy()).max()
+    ep = np.abs(phi1[:, k, j, i] - ophi.numpy()).max()
+    print(f"fp64 model {model}: {len(nodes)} nodes, max |df| {ef:.3e}, max |dphi| {ep:.3e}", flush=True)
+    assert ef < 1e-13 and ep < 1e-13
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("model", [0, 1, 2])
+def test_benchmark_size_fp32_against_fp64_100_steps(model):
+    """FP32 storage against FP64 storage (itself tied to the oracle above and
+    by the 500-step parity) on the full 1024 x 64 x 128 lock exchange after
+    100 steps: moments within 1e-5 of each field's infinity norm (velocity
+    components against the velocity magnitude's), the front within 1e-5."""
+    from tests.gpu_helpers import moment_errors
+    out = {}
+    for st in (pkg.F64, pkg.F32):
+        lat = pkg.Lattice(pkg.Config(storage=st, model=model, **BENCH))
+        lat.init_lock_exchange(0.125, 1e-3, 0)
+        lat.step(100)
+        out[st] = (gpu_moments(lat), lat.diagnostics())
+        lat.close()
+        torch.cuda.empty_cache()
+    errs = moment_errors(out[pkg.F32][0], out[pkg.F64][0])
+    d32, d64 = out[pkg.F32][1], out[pkg.F64][1]
+    print(f"model {model}: fp32 vs fp64 after 100 steps {errs}; x_front {d32['x_front']} vs {d64['x_front']}",
+          flush=True)
+    assert max(errs.values()) < 1e-5
+    assert abs(d32["x_front"] - d64["x_front"]) <= 1e-5 * d64["x_front"]
 
 
 @pytest.mark.timeout(900)

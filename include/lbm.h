@@ -8,11 +8,14 @@
  * Eq. 11, with half-way bounce-back walls (no slip, no flux) at x = 0, x = nx,
  * z = 0, z = nz and a periodic span y (Sec. 2.5).
  *
- *   model LBM_CUMULANT27_Q7 : D3Q27 cumulant collision (Eq. 36, 54-58) and a
- *                             D3Q7 BGK scalar (Eq. 28-30 on D3Q6 + rest)
- *   model LBM_BGK19_SMAG_Q6 : D3Q19 BGK + Guo forcing (Eq. 21-26) with
- *                             Smagorinsky eddy viscosity (Eq. 32-35) and a
- *                             D3Q6 BGK scalar (Eq. 28-31)
+ *   model LBM_CUMULANT27_Q7    : D3Q27 cumulant collision (Eq. 36, 54-58)
+ *                                and a D3Q7 BGK scalar (Eq. 28-30 on D3Q6 +
+ *                                rest)
+ *   model LBM_BGK19_SMAG_Q6    : D3Q19 BGK + Guo forcing (Eq. 21-26) with
+ *                                Smagorinsky eddy viscosity (Eq. 32-35) and
+ *                                a D3Q6 BGK scalar (Eq. 28-31)
+ *   model LBM_CUMULANT27_FCM27 : the D3Q27 cumulant collision and a D3Q27
+ *                                factorized-central-moment scalar (Eq. 37-51)
  *
  * Conventions shared by every entry point
  *   - Every function returns 0 (LBM_OK) or a negative LBM_E* code and never
@@ -26,8 +29,11 @@
  *     lbm_checkpoint_load and lbm_adjoint_run synchronise that stream.
  *   - Node (i, j, k) has linear index i + nx (j + ny k); x = i is the
  *     streamwise direction, y = j the span, z = k the vertical (gravity
- *     along -z, Eq. 10). Population arrays use the layout
- *     [population][k][j][i] (structure of arrays, i fastest).
+ *     along -z, Eq. 10). Fields passed in or out (chi0, moments, gradients,
+ *     wall stress) use that index. The population buffers inside the
+ *     workspace are x-blocked: element (a, i, row = j + ny k) sits at
+ *     (row ceil(nx/64) + i/64) (qt 64) + 64 a + i % 64; they are reached only
+ *     through the calls below (checkpoints copy them whole).
  *   - Population order (for the get/set hooks): D3Q19 in the order printed
  *     in Eq. 23; D3Q27 = that list followed by the corners (1,1,1),
  *     (-1,-1,-1), (1,1,-1), (-1,-1,1), (1,-1,1), (-1,1,-1), (1,-1,-1),

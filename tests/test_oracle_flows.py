@@ -1,5 +1,5 @@
-"""Closed-form pins of the oracle's full time step: shear-wave decay (viscosity,
-Eq. 25 and 58), Poiseuille flow between half-way bounce-back walls, exact
+"""Closed-form pins of the oracle's full time step: shear-wave and
+Taylor-Green vortex decay (viscosity, Eq. 25 and 58), Poiseuille flow between half-way bounce-back walls, exact
 variance growth of a diffusing scalar (Eq. 30), rest invariance, hydrostatic
 balance under the Boussinesq force, conservation and span symmetry."""
 import math
@@ -61,6 +61,47 @@ def test_shear_wave_viscosity_second_order(model):
         nu_eff, nu = _shear_wave_nu(model, L, 0.8)
         errs.append(abs(nu_eff / nu - 1))
     assert errs[1] < 3e-3
+    assert errs[0] / errs[1] > 3.0
+
+
+def _taylor_green_nu(model, L, tau, steps):
+    """2-D Taylor-Green vortex in the x-z plane of a periodic box,
+    u = U sin(kx) cos(kz), w = -U cos(kx) sin(kz): a solution of the
+    incompressible Navier-Stokes equations whose kinetic energy decays as
+    exp(-4 nu k^2 t) (each velocity amplitude as exp(-2 nu k^2 t))."""
+    P = derive(Config(L, 1, L, model=model, g_prime=0.0, nu_lu=(tau - 0.5) / 3,
+                      periodic_x=True, periodic_z=True))
+    k = 2 * math.pi / L
+    x = torch.arange(L, dtype=torch.float64)
+    X = x[None, None, :].expand(L, 1, L)
+    Z = x[:, None, None].expand(L, 1, L)
+    U = 0.01
+    u = torch.zeros(3, L, 1, L, dtype=torch.float64)
+    u[0] = U * torch.sin(k * X) * torch.cos(k * Z)
+    u[2] = -U * torch.cos(k * X) * torch.sin(k * Z)
+    # pressure of the vortex: p = rho U^2 (cos 2kx + cos 2kz) / 4, rho = 1 + 3 p
+    rho = 1.0 + 3.0 * U * U * (torch.cos(2 * k * X) + torch.cos(2 * k * Z)) / 4.0
+    f = _equilibrium(P, rho, u)
+    phi = torch.zeros(P.scal.Q, L, 1, L, dtype=torch.float64)
+    amps = {}
+    for n in range(steps[1] + 1):
+        if n in steps:
+            _, uu, _ = lbm.moments(f, phi, P)
+            amps[n] = float((uu[0] * torch.sin(k * X) * torch.cos(k * Z)).sum() * 4 / (L * L))
+        f, phi = lbm.step(f, phi, P)
+    nu_eff = -math.log(amps[steps[1]] / amps[steps[0]]) / (2 * k * k * (steps[1] - steps[0]))
+    return nu_eff, P.nu0
+
+
+@pytest.mark.parametrize("model", [0, 1])
+def test_taylor_green_vortex_decay_second_order(model):
+    """nu from the decay of the vortex -> (tau - 1/2)/3 (Eq. 25, 58), error
+    falling about 4x per doubling of the box (time scaled diffusively)."""
+    errs = []
+    for L, steps in ((12, (10, 70)), (24, (40, 280))):
+        nu_eff, nu = _taylor_green_nu(model, L, 0.8, steps)
+        errs.append(abs(nu_eff / nu - 1))
+    assert errs[1] < 5e-3
     assert errs[0] / errs[1] > 3.0
 
 

@@ -13,7 +13,9 @@ Modules
   params    lattice-unit parameters (Sec. 2.5, Eq. 25, 30)
   ring      truncated moment-generating-function ring: cumulants (Eq. 54)
   collide   BGK + Guo (Eq. 21-26), Smagorinsky (Eq. 32-35), cumulant
-            (Eq. 54-58), scalar BGK (Eq. 28-30)
+            (Eq. 54-58) with given or parametrised higher-order rates
+            (Sec. 2.3), scalar BGK (Eq. 28-30), factorized central moments
+            (Eq. 37-51)
   lbm       gather with half-way bounce-back / periodic span, initial state,
             one time step (Eq. 17), moments (Eq. 18-20, 27)
   diag      mass, scalar mass, bottom-wall friction (Eq. 62, 64) and front

@@ -146,7 +146,8 @@ def collide_cumulant(f, rho, j, F, P, cs_smag):
        cumulants C_110, C_101, C_011, C_200 - C_020, C_200 - C_002 with
        w1 = 1/tau_f (Eq. 58) towards 0; the trace C_200 + C_020 + C_002 with
        omega_bulk towards 1 (= 3 cs^2); every cumulant of order 3..6 with
-       omega3..omega6 towards 0;
+       omega3..omega6 towards 0, or, for the parametrised method the paper's
+       VirtualFluids runs use, as in ``relax_parametrized``;
     d. density is conserved (Eq. 56) and the force enters the first-order
        cumulants: C*_1 = (j + F) / rho, so that sum c f* = j + F (Eq. 17);
     e. back through exp and the inverse of the moment map.
@@ -176,19 +177,109 @@ def collide_cumulant(f, rho, j, F, P, cs_smag):
     Cs[1, 1, 0] = (1 - w1) * C[1, 1, 0]
     Cs[1, 0, 1] = (1 - w1) * C[1, 0, 1]
     Cs[0, 1, 1] = (1 - w1) * C[0, 1, 1]
-    rates = {3: cfg.omega3, 4: cfg.omega4, 5: cfg.omega5, 6: cfg.omega6}
-    for i in range(3):
-        for jj in range(3):
-            for k in range(3):
-                o = i + jj + k
-                if o >= 3:
-                    Cs[i, jj, k] = (1 - rates[o]) * C[i, jj, k]
+    if cfg.parametrized:
+        relax_parametrized(C, Cs, w1, w2, cfg.limiter)
+    else:
+        rates = {3: cfg.omega3, 4: cfg.omega4, 5: cfg.omega5, 6: cfg.omega6}
+        for i in range(3):
+            for jj in range(3):
+                for k in range(3):
+                    o = i + jj + k
+                    if o >= 3:
+                        Cs[i, jj, k] = (1 - rates[o]) * C[i, jj, k]
     js = j + F
     Cs[1, 0, 0] = js[0] / rho
     Cs[0, 1, 0] = js[1] / rho
     Cs[0, 0, 1] = js[2] / rho
     fstar = populations_from_raw(ring.moments_from_cumulants(Cs) * rho, lat)
     return fstar, tau
+
+
+def parametrized_rates(w1, w2):
+    """Rates and coefficients of the parametrised cumulant method that the
+    paper applies (Sec. 2.3, VirtualFluids; its reference 55: Geier, Pasquali
+    and Schoenherr, J. Comput. Phys. 348, 2017). The third-order rates are
+    chosen so that the leading error of the shear diffusion vanishes; A and B
+    set the fourth-order equilibria. w1: shear rate (Eq. 58), w2: bulk rate.
+
+    Returns (w_plus, w_minus, w_111, A, B): w_plus relaxes the sums
+    C_120 + C_102, C_210 + C_012, C_201 + C_021; w_minus their differences;
+    w_111 relaxes C_111. A and B are singular at w1 = w2.
+    """
+    w_plus = 8 * (w1 - 2) * (w2 * (3 * w1 - 1) - 5 * w1) / (
+        8 * (5 - 2 * w1) * w1 + w2 * (8 + w1 * (9 * w1 - 26)))
+    w_minus = 8 * (w1 - 2) * (w1 + w2 * (3 * w1 - 7)) / (
+        w2 * (56 - 42 * w1 + 9 * w1 * w1) - 8 * w1)
+    w_111 = 24 * (w1 - 2) * (4 * w1 * w1 + w1 * w2 * (18 - 13 * w1)
+                             + w2 * w2 * (2 + w1 * (6 * w1 - 11))) / (
+        16 * w1 * w1 * (w1 - 6) - 2 * w1 * w2 * (216 + 5 * w1 * (9 * w1 - 46))
+        + w2 * w2 * (w1 * (3 * w1 - 10) * (15 * w1 - 28) - 48))
+    den = (w1 - w2) * (w2 * (2 + 3 * w1) - 8 * w1)
+    A = (4 * w1 * w1 + 2 * w1 * w2 * (w1 - 6) + w2 * w2 * (w1 * (10 - 3 * w1) - 4)) / den
+    B = (4 * w1 * w2 * (9 * w1 - 16) - 4 * w1 * w1
+         - 2 * w2 * w2 * (2 + 9 * w1 * (w1 - 2))) / (3 * den)
+    return w_plus, w_minus, w_111, A, B
+
+
+def velocity_gradients(C, w1, w2):
+    """Velocity gradients estimated from the pre-collision second-order
+    cumulants C (of f / rho) at first order of the Chapman-Enskog expansion:
+    the non-equilibrium part of C_ab is -(d_a u_b + d_b u_a) / (3 w), with the
+    shear rate w1 for the deviatoric part and the bulk rate w2 for the trace
+    (whose equilibrium value is 3 cs^2 = 1). Returns
+    (dxux, dyuy, dzuz, Dxy, Dxz, Dyz), D_ab = d_a u_b + d_b u_a."""
+    cxx, cyy, czz = C[2, 0, 0], C[0, 2, 0], C[0, 0, 2]
+    div = -1.5 * w2 * (cxx + cyy + czz - 1.0)           # d_a u_a
+    dx_dy = -1.5 * w1 * (cxx - cyy)                     # d_x u_x - d_y u_y
+    dx_dz = -1.5 * w1 * (cxx - czz)                     # d_x u_x - d_z u_z
+    dxux = (div + dx_dy + dx_dz) / 3.0
+    dyuy = dxux - dx_dy
+    dzuz = dxux - dx_dz
+    return (dxux, dyuy, dzuz, -3.0 * w1 * C[1, 1, 0], -3.0 * w1 * C[1, 0, 1],
+            -3.0 * w1 * C[0, 1, 1])
+
+
+def relax_parametrized(C, Cs, w1, w2, limiter):
+    """Orders 3..6 of the parametrised cumulant collision (Eq. 55 with the
+    rates and equilibria of ``parametrized_rates``), written into Cs.
+
+    * third order: the sums and differences of the pairs (C_120, C_102),
+      (C_210, C_012), (C_201, C_021) relax towards 0 with w_plus and w_minus,
+      C_111 with w_111. With a limiter lambda > 0 each rate w becomes
+      w + (1 - w) |X| / (|X| + lambda) for its own quantity X (cumulants of
+      f / rho, so lambda plays the part of rho lambda for cumulants of f): large
+      third-order cumulants relax at rate 1 (Sec. 2.3, the stabilised method);
+    * fourth order relaxes with rate 1 onto equilibria proportional to the
+      velocity gradients: C_220 = -(2/3)(1/w1 - 1/2) A (d_x u_x + d_y u_y),
+      C_211 = -(1/3)(1/w1 - 1/2) B (d_y u_z + d_z u_y) and their permutations;
+    * fifth and sixth order relax with rate 1 towards 0.
+    """
+    w_plus, w_minus, w_111, A, B = parametrized_rates(w1, w2)
+
+    def keep(w, X):                      # 1 - (limited rate)
+        if limiter > 0:
+            a = X.abs()
+            return (1 - w) * (1 - a / (a + limiter))
+        return 1 - w
+
+    for a, b in (((1, 2, 0), (1, 0, 2)), ((2, 1, 0), (0, 1, 2)), ((2, 0, 1), (0, 2, 1))):
+        plus = C[a] + C[b]
+        minus = C[a] - C[b]
+        plus = keep(w_plus, plus) * plus
+        minus = keep(w_minus, minus) * minus
+        Cs[a] = 0.5 * (plus + minus)
+        Cs[b] = 0.5 * (plus - minus)
+    Cs[1, 1, 1] = keep(w_111, C[1, 1, 1]) * C[1, 1, 1]
+    dxux, dyuy, dzuz, Dxy, Dxz, Dyz = velocity_gradients(C, w1, w2)
+    h = 1.0 / w1 - 0.5
+    Cs[2, 2, 0] = -(2.0 / 3.0) * h * A * (dxux + dyuy)
+    Cs[2, 0, 2] = -(2.0 / 3.0) * h * A * (dxux + dzuz)
+    Cs[0, 2, 2] = -(2.0 / 3.0) * h * A * (dyuy + dzuz)
+    Cs[2, 1, 1] = -(1.0 / 3.0) * h * B * Dyz
+    Cs[1, 2, 1] = -(1.0 / 3.0) * h * B * Dxz
+    Cs[1, 1, 2] = -(1.0 / 3.0) * h * B * Dxy
+    for idx in ((2, 2, 1), (2, 1, 2), (1, 2, 2), (2, 2, 2)):
+        Cs[idx] = torch.zeros_like(C[idx])
 
 
 def collide_scalar(phi, chi, u, tau_phi, P):

@@ -39,6 +39,11 @@ class Config:
     omega4: float = 1.0
     omega5: float = 1.0
     omega6: float = 1.0
+    # parametrised cumulant (Sec. 2.3, VirtualFluids): third-order rates and
+    # fourth-order equilibria from omega1 and omega_bulk; limiter lambda of the
+    # third-order relaxation, 0 = no limiter
+    parametrized: bool = False
+    limiter: float = 0.0
     # oracle-only switches for the closed-form checks (the product has walls)
     periodic_x: bool = False
     periodic_z: bool = False

@@ -31,6 +31,12 @@ WORKLOADS = {
     "bgk19_smag_q6_1024x64x128_fp32": dict(nx=1024, ny=64, nz=128, model=1, storage="f32"),
     "cumulant27_fcm27_1024x64x128_fp32": dict(nx=1024, ny=64, nz=128, model=2, storage="f32"),
     "cumulant27_fcm27_2048x128x256_fp16": dict(nx=2048, ny=128, nz=256, model=2, storage="f16"),
+    # the parametrised cumulant with the third-order limiter and no LES (the
+    # paper's VirtualFluids configuration)
+    "cumulant27param_fcm27_1024x64x128_fp32": dict(nx=1024, ny=64, nz=128, model=2, storage="f32",
+                                                   param=True),
+    "cumulant27param_fcm27_2048x128x256_fp16": dict(nx=2048, ny=128, nz=256, model=2, storage="f16",
+                                                    param=True),
     "cumulant27_q7_2048x128x256_fp32": dict(nx=2048, ny=128, nz=256, model=0, storage="f32"),
     "cumulant27_q7_2048x128x256_fp16": dict(nx=2048, ny=128, nz=256, model=0, storage="f16"),
     "cumulant27_q7_2048x128x256_bf16": dict(nx=2048, ny=128, nz=256, model=0, storage="bf16"),
@@ -43,7 +49,8 @@ HEADLINE = "cumulant27_q7_1024x64x128_fp32"
 VARIANTS = ["cumulant27_q7_2048x128x256_fp16", "cumulant27_q7_2048x128x256_bf16",
             "cumulant27_q7_2048x128x256_bf16_f16s", "cumulant27_q7_4096x256x512_fp16",
             "bgk19_smag_q6_1024x64x128_fp32", "cumulant27_fcm27_1024x64x128_fp32",
-            "cumulant27_fcm27_2048x128x256_fp16"]
+            "cumulant27_fcm27_2048x128x256_fp16", "cumulant27param_fcm27_1024x64x128_fp32",
+            "cumulant27param_fcm27_2048x128x256_fp16"]
 
 
 def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0):
@@ -125,8 +132,10 @@ def measure(name, steps, warmup):
     import paper_2112_08479_amd as pkg
     w = WORKLOADS[name]
     st = {"f64": pkg.F64, "f32": pkg.F32, "f16": pkg.F16, "bf16": pkg.BF16, "bf16_f16s": pkg.BF16_F16S}[w["storage"]]
+    par = w.get("param", False)
     cfg = pkg.Config(w["nx"], w["ny"], w["nz"], model=w["model"], storage=st, re_b=30000.0,
-                     g_prime=1e-4, cs_smag=0.1, sc_t=1.0)
+                     g_prime=1e-4, cs_smag=0.0 if par else 0.1, sc_t=1.0, parametrized=par,
+                     limiter=1e-2 if par else 0.0)
     lat = pkg.Lattice(cfg)
     lat.init_lock_exchange(0.125, 1e-3, 0)
     lat.step(warmup)
@@ -276,7 +285,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "nx": w["nx"], "ny": w["ny"], "nz": w["nz"],
                    "model": ["cumulant27_q7", "bgk19_smag_q6", "cumulant27_fcm27"][w["model"]], "re_b": 30000.0,
-                   "cs_smag": 0.1, "sc_t": 1.0, "g_prime": 1e-4, "parallelism": "single-gpu"},
+                   "cs_smag": 0.0 if w.get("param") else 0.1, "sc_t": 1.0, "g_prime": 1e-4,
+                   "cumulant_rates": "parametrised, limiter 1e-2" if w.get("param") else "omega3..6 = 1",
+                   "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_for(args.workload, launch_bytes)},

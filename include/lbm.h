@@ -88,8 +88,10 @@ enum { LBM_OUT_F32 = 1, LBM_OUT_F64 = 0 };
 typedef struct {
   uint32_t struct_size;   /* must be sizeof(lbm_config) */
   int32_t nx, ny, nz;     /* nodes; depth H = nz lattice units */
-  int32_t model;          /* LBM_CUMULANT27_Q7 or LBM_BGK19_SMAG_Q6 */
-  int32_t storage;        /* LBM_F64 / LBM_F32 / LBM_F16 / LBM_BF16 */
+  int32_t model;          /* LBM_CUMULANT27_Q7, LBM_BGK19_SMAG_Q6 or
+                             LBM_CUMULANT27_FCM27 */
+  int32_t storage;        /* LBM_F64 / LBM_F32 / LBM_F16 / LBM_BF16 /
+                             LBM_BF16_F16S */
   double re_b;            /* buoyancy Reynolds number U_b H / nu0 (Eq. 12-14) */
   double sc;              /* Schmidt number nu0 / D0 */
   double g_prime;         /* reduced gravity, lattice units */
@@ -99,6 +101,21 @@ typedef struct {
   double sc_t;            /* turbulent Schmidt number */
   double omega_bulk;      /* cumulant trace (bulk) relaxation rate, (0, 2) */
   double omega3, omega4, omega5, omega6; /* cumulant rates of order 3..6 */
+  /* 1: the parametrised cumulant of the paper's VirtualFluids runs (Sec. 2.3;
+   * the method of Geier, Pasquali and Schoenherr, J. Comput. Phys. 348,
+   * 2017): the third-order rates are functions of omega1 = 1/tau0 and
+   * omega_bulk chosen for fourth-order accurate shear diffusion
+   * (lbm_params.w_plus, w_minus, w_111), the fourth-order cumulants relax
+   * with rate 1 onto equilibria proportional to the velocity gradients
+   * (coefficients coef_a, coef_b), orders 5 and 6 with rate 1 towards 0.
+   * Needs a cumulant model, cs_smag = 0 (the method runs without a sub-grid
+   * model), omega3..omega6 = 1 (they are replaced), omega1 != omega_bulk and
+   * finite rates. 0: every cumulant of order n relaxes with omega_n. */
+  int32_t parametrized;
+  /* limiter lambda of the third-order relaxation in parametrised mode: each
+   * rate w becomes w + (1 - w)|X| / (|X| + lambda) for its own third-order
+   * quantity X (a cumulant of f / rho); 0 = no limiter; >= 0 */
+  double limiter;
 } lbm_config;
 
 /* Derived lattice-unit parameters (Sec. 2.5, Eq. 25, 30). */
@@ -111,6 +128,10 @@ typedef struct {
   double tau_phi0;  /* 1/2 + D0 / cs_phi^2 */
   double cs2_phi;   /* 1/4 (D3Q7) or 1/3 (D3Q6, D3Q27) */
   int32_t q_flow, q_scalar;
+  /* parametrised cumulant (0 unless lbm_config.parametrized): rates of
+   * C_120 + C_102 (and permutations), of C_120 - C_102 (and permutations)
+   * and of C_111; fourth-order equilibrium coefficients A and B */
+  double w_plus, w_minus, w_111, coef_a, coef_b;
 } lbm_params;
 
 /* Diagnostics of the state at the current step (pre-collision moments):
@@ -219,8 +240,9 @@ int lbm_set_populations(lbm_handle* h, const double* host_f, const double* host_
  * *dJ_dsct (Sc_T) as host doubles and dJ/dchi0 (nx*ny*nz doubles, device;
  * chi0 enters through phi(0) = w_phi chi0). Non-smooth points: zero
  * subgradient of sqrt(Q) at Q = 0; the front uses the active column i* and
- * the first depth maximum. Requires omega3..omega6 = 1 for the cumulant models
- * and storage LBM_F32 or LBM_F64 (LBM_EINVAL otherwise); LBM_ESTATE if the
+ * the first depth maximum. Requires omega3..omega6 = 1 and parametrized = 0
+ * for the cumulant models and storage LBM_F32 or LBM_F64 (LBM_EINVAL
+ * otherwise); LBM_ESTATE if the
  * handle is not at step 0. adj_ws: device scratch of
  * lbm_adjoint_workspace_bytes(cfg, n, k_ckpt) bytes (LBM_ENOMEM if smaller).
  * Leaves the handle at step n. Synchronises. */

@@ -47,13 +47,16 @@ class c_config(ctypes.Structure):
                 ("re_b", ctypes.c_double), ("sc", ctypes.c_double), ("g_prime", ctypes.c_double),
                 ("ub_lu", ctypes.c_double), ("cs_smag", ctypes.c_double), ("sc_t", ctypes.c_double),
                 ("omega_bulk", ctypes.c_double), ("omega3", ctypes.c_double),
-                ("omega4", ctypes.c_double), ("omega5", ctypes.c_double), ("omega6", ctypes.c_double)]
+                ("omega4", ctypes.c_double), ("omega5", ctypes.c_double), ("omega6", ctypes.c_double),
+                ("parametrized", ctypes.c_int32), ("limiter", ctypes.c_double)]
 
 
 class c_params(ctypes.Structure):
     _fields_ = [("u_b", ctypes.c_double), ("g_prime", ctypes.c_double), ("nu0", ctypes.c_double),
                 ("tau0", ctypes.c_double), ("d0", ctypes.c_double), ("tau_phi0", ctypes.c_double),
-                ("cs2_phi", ctypes.c_double), ("q_flow", ctypes.c_int32), ("q_scalar", ctypes.c_int32)]
+                ("cs2_phi", ctypes.c_double), ("q_flow", ctypes.c_int32), ("q_scalar", ctypes.c_int32),
+                ("w_plus", ctypes.c_double), ("w_minus", ctypes.c_double), ("w_111", ctypes.c_double),
+                ("coef_a", ctypes.c_double), ("coef_b", ctypes.c_double)]
 
 
 class c_diag(ctypes.Structure):
@@ -131,12 +134,15 @@ class Config:
     omega4: float = 1.0
     omega5: float = 1.0
     omega6: float = 1.0
+    parametrized: bool = False     # parametrised cumulant (third-order rates from omega1)
+    limiter: float = 0.0           # third-order limiter lambda; 0 = none
 
     def c(self):
         s = c_config()
         s.struct_size = ctypes.sizeof(c_config)
         for f in c_config._fields_[1:]:
-            setattr(s, f[0], getattr(self, f[0]))
+            v = getattr(self, f[0])
+            setattr(s, f[0], int(v) if f[1] is ctypes.c_int32 else v)
         return s
 
     @property

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <utility>
 
@@ -81,6 +82,30 @@ Layout layout_of(const lbm_config* c, const lbm_params* p) {
   return L;
 }
 
+// Third-order rates and fourth-order equilibrium coefficients of the
+// parametrised cumulant (Geier, Pasquali and Schoenherr 2017, the method the
+// paper's VirtualFluids runs apply, Sec. 2.3) for shear rate w1 and bulk rate
+// w2. false if a denominator vanishes or a value is not finite.
+bool parametrized_rates(double w1, double w2, lbm_params* p) {
+  const double w1s = w1 * w1, w2s = w2 * w2;
+  const double dp = 8.0 * (5.0 - 2.0 * w1) * w1 + w2 * (8.0 + w1 * (9.0 * w1 - 26.0));
+  const double dm = w2 * (56.0 - 42.0 * w1 + 9.0 * w1s) - 8.0 * w1;
+  const double dd = 16.0 * w1s * (w1 - 6.0) - 2.0 * w1 * w2 * (216.0 + 5.0 * w1 * (9.0 * w1 - 46.0)) +
+                    w2s * (w1 * (3.0 * w1 - 10.0) * (15.0 * w1 - 28.0) - 48.0);
+  const double dab = (w1 - w2) * (w2 * (2.0 + 3.0 * w1) - 8.0 * w1);
+  const double tiny = 1e-12;
+  if (fabs(dp) < tiny || fabs(dm) < tiny || fabs(dd) < tiny || fabs(dab) < tiny) return false;
+  p->w_plus = 8.0 * (w1 - 2.0) * (w2 * (3.0 * w1 - 1.0) - 5.0 * w1) / dp;
+  p->w_minus = 8.0 * (w1 - 2.0) * (w1 + w2 * (3.0 * w1 - 7.0)) / dm;
+  p->w_111 = 24.0 * (w1 - 2.0) *
+             (4.0 * w1s + w1 * w2 * (18.0 - 13.0 * w1) + w2s * (2.0 + w1 * (6.0 * w1 - 11.0))) / dd;
+  p->coef_a = (4.0 * w1s + 2.0 * w1 * w2 * (w1 - 6.0) + w2s * (w1 * (10.0 - 3.0 * w1) - 4.0)) / dab;
+  p->coef_b = (4.0 * w1 * w2 * (9.0 * w1 - 16.0) - 4.0 * w1s - 2.0 * w2s * (2.0 + 9.0 * w1 * (w1 - 2.0))) /
+              (3.0 * dab);
+  return std::isfinite(p->w_plus) && std::isfinite(p->w_minus) && std::isfinite(p->w_111) &&
+         std::isfinite(p->coef_a) && std::isfinite(p->coef_b);
+}
+
 int validate(const lbm_config* c, lbm_params* out) {
   if (!c) return fail(LBM_EINVAL, "config is NULL");
   if (c->struct_size != sizeof(lbm_config))
@@ -113,6 +138,22 @@ int validate(const lbm_config* c, lbm_params* out) {
   p.q_scalar = c->model == LBM_CUMULANT27_Q7 ? 7 : (c->model == LBM_BGK19_SMAG_Q6 ? 6 : 27);
   if (!(p.tau0 > 0.5))
     return fail(LBM_EINVAL, "tau0 = %.17g must be > 1/2 (g' = 0 or Re_b too large)", p.tau0);
+  p.w_plus = p.w_minus = p.w_111 = p.coef_a = p.coef_b = 0.0;
+  if (c->parametrized != 0 && c->parametrized != 1)
+    return fail(LBM_EINVAL, "parametrized must be 0 or 1");
+  if (!(c->limiter >= 0) || std::isinf(c->limiter))
+    return fail(LBM_EINVAL, "limiter must be finite and >= 0");
+  if (c->parametrized) {
+    if (c->model == LBM_BGK19_SMAG_Q6)
+      return fail(LBM_EINVAL, "the parametrised rates need a cumulant model");
+    if (c->cs_smag != 0.0)
+      return fail(LBM_EINVAL, "the parametrised cumulant runs without the Smagorinsky model (cs_smag = 0)");
+    if (c->omega3 != 1.0 || c->omega4 != 1.0 || c->omega5 != 1.0 || c->omega6 != 1.0)
+      return fail(LBM_EINVAL, "parametrised mode replaces omega3..omega6: leave them at 1");
+    if (!parametrized_rates(1.0 / p.tau0, c->omega_bulk, &p))
+      return fail(LBM_EINVAL, "parametrised rates are singular or not finite at omega1 = %.17g, "
+                  "omega_bulk = %.17g", 1.0 / p.tau0, c->omega_bulk);
+  }
   if (out) *out = p;
   return LBM_OK;
 }
@@ -181,6 +222,8 @@ int adjoint_supported(const lbm_config* c) {
   if (c->model != LBM_BGK19_SMAG_Q6 &&
       (c->omega3 != 1.0 || c->omega4 != 1.0 || c->omega5 != 1.0 || c->omega6 != 1.0))
     return fail(LBM_EINVAL, "the cumulant adjoint needs omega3..omega6 = 1");
+  if (c->parametrized)
+    return fail(LBM_EINVAL, "the adjoint does not cover the parametrised cumulant");
   return LBM_OK;
 }
 }  // namespace

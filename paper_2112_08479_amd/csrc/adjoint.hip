@@ -377,6 +377,9 @@ static Phys<CT> aphys(const lbm_handle* h) {
   r.omega4 = (CT)c.omega4;
   r.omega5 = (CT)c.omega5;
   r.omega6 = (CT)c.omega6;
+  // the adjoint runs only with the fixed rates (parametrised mode is rejected)
+  r.w_plus = r.w_minus = r.w_111 = r.a4 = r.b4 = (CT)0;
+  r.lam = (CT)INFINITY;
   return r;
 }
 

@@ -37,6 +37,10 @@ struct Phys {
   CT inv_sct;     // 1 / Sc_T
   CT inv_cs2phi;  // 1 / cs_phi^2
   CT omega2, omega3, omega4, omega5, omega6;
+  // parametrised cumulant: third-order rates, fourth-order equilibrium
+  // factors -(2/3)(1/omega1 - 1/2) A and -(1/3)(1/omega1 - 1/2) B, limiter
+  // lambda (+inf: none)
+  CT w_plus, w_minus, w_111, a4, b4, lam;
 };
 
 // one-dimensional rest central moments k_c and weights w(c), c = -1, 0, 1
@@ -329,9 +333,20 @@ LBM_HD void collide_cumulant27(CT* g, CT* ph, const Phys<CT>& p, CT* tau_out = n
   scalar_collision<LS, LES>(ph, chi, ux, uy, (jz + CT(0.5) * Fz) * irho, tau, p);
 }
 
-// ---- cumulant collision with general rates omega3..omega6.
-template <class LS, bool LES, typename CT>
+// ---- cumulant collision with general rates omega3..omega6 (PARAM false) or
+// the parametrised cumulant of Geier, Pasquali and Schoenherr (2017) that the
+// paper's VirtualFluids runs apply (Sec. 2.3; PARAM true, no LES):
+//   third order: the sums C_120 + C_102 (and permutations) relax with w_plus,
+//     the differences with w_minus, C_111 with w_111, each limited to
+//     w + (1 - w)|X| / (|X| + lambda) for its own quantity X;
+//   fourth order: rate 1 onto equilibria proportional to the velocity
+//     gradients, estimated from the pre-collision second-order cumulants at
+//     first Chapman-Enskog order (non-equilibrium part of C_ab =
+//     -(d_a u_b + d_b u_a) / (3 w), w = omega1 deviatoric, omega_bulk trace);
+//   fifth and sixth order: rate 1 towards 0.
+template <class LS, bool LES, typename CT, bool PARAM = false>
 LBM_HD void collide_cumulant27_general(CT* g, CT* ph, const Phys<CT>& p) {
+  static_assert(!(PARAM && LES), "the parametrised cumulant runs without the LES");
   CT drho = CT(0), jx = CT(0), jy = CT(0), jz = CT(0);
   static_for<0, 27>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
@@ -390,15 +405,50 @@ LBM_HD void collide_cumulant27_general(CT* g, CT* ph, const Phys<CT>& p) {
     tau = smagorinsky_tau(q2, p);
   }
   const CT a1 = CT(1) - CT(1) / tau;
+  CT C210, C201, C120, C021, C102, C012, C111;
+  CT C220, C202, C022, C211, C121, C112, C221, C212, C122, C222;
+  if constexpr (PARAM) {
+    // velocity gradients from the pre-collision second-order cumulants
+    // (dxx.. are C_ab - delta_ab / 3, so the trace deviation is their sum)
+    const CT w1 = CT(1) / tau;
+    const CT div = CT(-1.5) * p.omega2 * (dxx + dyy + dzz);
+    const CT dxy_d = CT(-1.5) * w1 * (dxx - dyy), dxz_d = CT(-1.5) * w1 * (dxx - dzz);
+    const CT dxux = (div + dxy_d + dxz_d) * third;
+    const CT dyuy = dxux - dxy_d, dzuz = dxux - dxz_d;
+    C220 = p.a4 * (dxux + dyuy);
+    C202 = p.a4 * (dxux + dzuz);
+    C022 = p.a4 * (dyuy + dzuz);
+    C112 = p.b4 * (CT(-3) * w1 * dxy);
+    C121 = p.b4 * (CT(-3) * w1 * dxz);
+    C211 = p.b4 * (CT(-3) * w1 * dyz);
+    // third order: 1 - limited rate = (1 - w)(1 - |X| / (|X| + lambda))
+    auto keep = [&](CT w, CT X) {
+      const CT a = X < CT(0) ? -X : X;
+      return (CT(1) - w) * (CT(1) - a / (a + p.lam));
+    };
+    auto pair = [&](CT a, CT b, CT& oa, CT& ob) {
+      CT s = a + b, d = a - b;
+      s *= keep(p.w_plus, s);
+      d *= keep(p.w_minus, d);
+      oa = CT(0.5) * (s + d);
+      ob = CT(0.5) * (s - d);
+    };
+    pair(m120, m102, C120, C102);
+    pair(m210, m012, C210, C012);
+    pair(m201, m021, C201, C021);
+    C111 = keep(p.w_111, m111) * m111;
+    C221 = C212 = C122 = C222 = CT(0);
+  } else {
+    const CT a3 = CT(1) - p.omega3, a4 = CT(1) - p.omega4, a5 = CT(1) - p.omega5,
+             a6 = CT(1) - p.omega6;
+    C210 = a3 * m210, C201 = a3 * m201, C120 = a3 * m120, C021 = a3 * m021;
+    C102 = a3 * m102, C012 = a3 * m012, C111 = a3 * m111;
+    C220 = a4 * c220, C202 = a4 * c202, C022 = a4 * c022;
+    C211 = a4 * c211, C121 = a4 * c121, C112 = a4 * c112;
+    C221 = a5 * c221, C212 = a5 * c212, C122 = a5 * c122;
+    C222 = a6 * c222;
+  }
   relax_second(a1, p.omega2, dxx, dyy, dzz, dxy, dxz, dyz);
-  const CT a3 = CT(1) - p.omega3, a4 = CT(1) - p.omega4, a5 = CT(1) - p.omega5,
-           a6 = CT(1) - p.omega6;
-  const CT C210 = a3 * m210, C201 = a3 * m201, C120 = a3 * m120, C021 = a3 * m021;
-  const CT C102 = a3 * m102, C012 = a3 * m012, C111 = a3 * m111;
-  const CT C220 = a4 * c220, C202 = a4 * c202, C022 = a4 * c022;
-  const CT C211 = a4 * c211, C121 = a4 * c121, C112 = a4 * c112;
-  const CT C221 = a5 * c221, C212 = a5 * c212, C122 = a5 * c122;
-  const CT C222 = a6 * c222;
   // moments from cumulants (zero mean), deviations from rest
   CT m[27];
   m[0] = drho;

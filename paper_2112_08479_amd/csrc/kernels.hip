@@ -106,8 +106,12 @@ __device__ __forceinline__ int block_order(int b, int nblocks, int nbx) {
 #define LBM_PERSIST 0
 #endif
 
-// one tile: NPT * blockDim.x consecutive nodes of one row
-template <int MODEL, typename ST, typename SS, typename CT, bool LES, bool GEN, int NPT>
+// collision kinds of the cumulant models
+enum { kCumFast = 0, kCumGeneral = 1, kCumParam = 2 };
+
+// one tile: NPT * blockDim.x consecutive nodes of one row; KIND: kCumFast
+// (omega3..omega6 = 1), kCumGeneral (given rates), kCumParam (parametrised)
+template <int MODEL, typename ST, typename SS, typename CT, bool LES, int KIND, int NPT>
 __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __restrict__ dst,
                                           const Grid& g, const Phys<CT>& p, int nbx, int b) {
   using LF = typename ModelT<MODEL>::LF;
@@ -123,7 +127,9 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     if constexpr (MODEL == 0 || MODEL == 2) {
-      if constexpr (GEN)
+      if constexpr (KIND == kCumParam)
+        collide_cumulant27_general<LS, false, CT, true>(fg[k], ph[k], p);
+      else if constexpr (KIND == kCumGeneral)
         collide_cumulant27_general<LS, LES, CT>(fg[k], ph[k], p);
       else
         collide_cumulant27<LS, LES, CT>(fg[k], ph[k], p);
@@ -153,16 +159,16 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
 #define LBM_STEP_WAVES 0
 #endif
 
-template <int MODEL, typename ST, typename SS, typename CT, bool LES, bool GEN, int NPT>
+template <int MODEL, typename ST, typename SS, typename CT, bool LES, int KIND, int NPT>
 __global__ __launch_bounds__(kBlock, LBM_STEP_WAVES) void k_step(const ST* __restrict__ src, ST* __restrict__ dst,
                                                  Grid g, Phys<CT> p, int nbx, int ntiles) {
 #if LBM_PERSIST
   for (int b = blockIdx.x; b < ntiles; b += gridDim.x)
-    step_tile<MODEL, ST, SS, CT, LES, GEN, NPT>(src, dst, g, p, nbx, b);
+    step_tile<MODEL, ST, SS, CT, LES, KIND, NPT>(src, dst, g, p, nbx, b);
 #else
   (void)ntiles;
-  step_tile<MODEL, ST, SS, CT, LES, GEN, NPT>(src, dst, g, p, nbx,
-                                              block_order(blockIdx.x, gridDim.x, nbx));
+  step_tile<MODEL, ST, SS, CT, LES, KIND, NPT>(src, dst, g, p, nbx,
+                                               block_order(blockIdx.x, gridDim.x, nbx));
 #endif
 }
 
@@ -560,6 +566,13 @@ static Phys<CT> phys_of(const lbm_handle* h) {
   r.omega4 = (CT)c.omega4;
   r.omega5 = (CT)c.omega5;
   r.omega6 = (CT)c.omega6;
+  const double h4 = p.tau0 - 0.5;  // 1/omega1 - 1/2
+  r.w_plus = (CT)p.w_plus;
+  r.w_minus = (CT)p.w_minus;
+  r.w_111 = (CT)p.w_111;
+  r.a4 = (CT)(-2.0 / 3.0 * h4 * p.coef_a);
+  r.b4 = (CT)(-1.0 / 3.0 * h4 * p.coef_b);
+  r.lam = c.limiter > 0.0 ? (CT)c.limiter : (CT)INFINITY;
   return r;
 }
 
@@ -586,15 +599,16 @@ static hipError_t with_model(const lbm_handle* h, F&& f) {
   return hipErrorInvalidValue;
 }
 
-static bool general_rates(const lbm_handle* h) {
+static int cumulant_kind(const lbm_handle* h) {
   const lbm_config& c = h->cfg;
-  return c.omega3 != 1.0 || c.omega4 != 1.0 || c.omega5 != 1.0 || c.omega6 != 1.0;
+  if (c.parametrized) return kCumParam;
+  return (c.omega3 != 1.0 || c.omega4 != 1.0 || c.omega5 != 1.0 || c.omega6 != 1.0) ? kCumGeneral
+                                                                                   : kCumFast;
 }
 
 template <int M, typename ST, typename SS, typename CT, int NPT>
 static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src, void* dst) {
   const bool les = h->cfg.cs_smag > 0.0;
-  const bool gen = general_rates(h);
   const int per_thread_x = (g.nx + NPT - 1) / NPT;  // x-extent in threads if one block
   const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
   const int nbx = (g.nx + bx * NPT - 1) / (bx * NPT);
@@ -607,16 +621,24 @@ static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src,
   const Phys<CT> p = phys_of<CT>(h);
   const ST* s = static_cast<const ST*>(src);
   ST* d = static_cast<ST*>(dst);
-  if (les) {
-    if (M != 1 && gen)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, true, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+  if constexpr (M == 1) {  // BGK: one collision kind
+    if (les)
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
     else
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, false, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
   } else {
-    if (M != 1 && gen)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, true, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+    // the parametrised kind never has the LES (rejected when the handle is made)
+    const int kind = cumulant_kind(h);
+    if (les && kind == kCumGeneral)
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+    else if (les)
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+    else if (kind == kCumParam)
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumParam, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+    else if (kind == kCumGeneral)
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
     else
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, false, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
   }
   return hipGetLastError();
 }

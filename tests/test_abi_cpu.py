@@ -76,6 +76,15 @@ BAD = [
     (dict(nx=8, ny=8, nz=16, cs_smag=-0.1), "C_s"),
     (dict(nx=8, ny=8, nz=16, omega3=2.0), "rates"),
     (dict(nx=8, ny=8, nz=16, omega_bulk=0.0), "rates"),
+    (dict(nx=8, ny=8, nz=16, model=1, parametrized=True), "cumulant model"),
+    (dict(nx=8, ny=8, nz=16, cs_smag=0.1, parametrized=True), "Smagorinsky"),
+    (dict(nx=8, ny=8, nz=16, omega4=1.2, parametrized=True), "omega3..omega6"),
+    (dict(nx=8, ny=8, nz=16, parametrized=True, limiter=-1e-3), "limiter"),
+    (dict(nx=8, ny=8, nz=16, parametrized=True, limiter=float("inf")), "limiter"),
+    (dict(nx=8, ny=8, nz=16, parametrized=2), "parametrized"),
+    # A and B are singular where the shear and bulk rates coincide
+    (dict(nx=8, ny=8, nz=16, re_b=1000.0, g_prime=1e-4, parametrized=True,
+          omega_bulk=1.0 / (3.0 * (1e-4 * 16) ** 0.5 * 16 / 1000.0 + 0.5)), "singular"),
 ]
 
 
@@ -123,7 +132,8 @@ def test_adjoint_is_declined_where_it_is_not_built():
     for model in (0, 1, 2):
         ok = pkg.Config(64, 4, 8, model=model, storage=pkg.F32, re_b=1000.0, cs_smag=0.1)
         assert pkg.lib().lbm_adjoint_workspace_bytes(ok.c(), 10, 5) > 0
-    for bad in (dict(model=2, omega3=0.9), dict(storage=pkg.F16), dict(omega4=1.2)):
+    for bad in (dict(model=2, omega3=0.9), dict(storage=pkg.F16), dict(omega4=1.2),
+                dict(model=2, cs_smag=0.0, parametrized=True, limiter=1e-2)):
         c = pkg.Config(**{**dict(nx=64, ny=4, nz=8, model=0, storage=pkg.F32, re_b=1000.0), **bad})
         assert pkg.lib().lbm_adjoint_workspace_bytes(c.c(), 10, 5) == 0
 
@@ -131,3 +141,21 @@ def test_adjoint_is_declined_where_it_is_not_built():
 def test_workspace_bytes_of_the_fcm_model_cover_54_arrays():
     cfg = pkg.Config(1024, 64, 128, model=2, storage=pkg.F32, re_b=30000.0)
     assert pkg.workspace_bytes(cfg) >= 2 * 54 * cfg.n * 4
+
+
+@pytest.mark.parametrize("kw", [dict(model=0, re_b=1000.0), dict(model=2, re_b=30000.0),
+                                dict(model=2, re_b=300.0, omega_bulk=1.4, limiter=1e-2)])
+def test_parametrized_rates_match_the_oracle(kw):
+    """The library's host derivation of the parametrised rates and
+    coefficients against the oracle's, written separately from the same
+    published formulas (the oracle's are pinned by the fourth-order shear
+    dispersion)."""
+    from oracle.collide import parametrized_rates
+    cfg = pkg.Config(1024, 64, 128, parametrized=True, **kw)
+    got = pkg.derive_params(cfg)
+    P = derive(OConfig(1024, 64, 128, parametrized=True, **kw))
+    want = parametrized_rates(1.0 / P.tau0, cfg.omega_bulk)
+    for k, w in zip(("w_plus", "w_minus", "w_111", "coef_a", "coef_b"), want):
+        assert math.isclose(got[k], w, rel_tol=1e-13), (k, got[k], w)
+    off = pkg.derive_params(pkg.Config(1024, 64, 128, **{**kw, "limiter": 0.0}))
+    assert off["w_plus"] == 0.0 and off["coef_b"] == 0.0

@@ -114,6 +114,37 @@ def test_benchmark_size_one_step_sampled(model):
     assert ef < 2e-7 and ep < (4e-7 if model == 2 else 2e-7)
 
 
+BENCH_PARAM = dict(nx=1024, ny=64, nz=128, re_b=30000.0, g_prime=1e-4, parametrized=True, limiter=1e-2)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("storage", [pkg.F64, pkg.F32])
+@pytest.mark.parametrize("model", [0, 2])
+def test_benchmark_size_parametrized_one_step_sampled(model, storage):
+    """The parametrised cumulant with the limiter (the paper's VirtualFluids
+    configuration for model 3) at 1024 x 64 x 128: one step after 20, at
+    sampled nodes, against the oracle."""
+    cfg, P = both(storage, model=model, **BENCH_PARAM)
+    lat = pkg.Lattice(cfg)
+    lat.init_lock_exchange(0.125, 1e-3, 0)
+    lat.step(20)
+    f0, phi0 = lat.get_populations()
+    lat.step(1)
+    f1, phi1 = lat.get_populations()
+    lat.close()
+    nodes = _sample_nodes(cfg.nx, cfg.ny, cfg.nz, seed=2)
+    torch.set_num_threads(max(1, min(16, torch.get_num_threads())))
+    of, ophi = olbm.step_at(torch.from_numpy(f0), torch.from_numpy(phi0), P, nodes)
+    k, j, i = (np.array(c) for c in zip(*nodes))
+    ef = np.abs(f1[:, k, j, i] - of.numpy()).max()
+    ep = np.abs(phi1[:, k, j, i] - ophi.numpy()).max()
+    print(f"parametrised model {model} storage {storage}: max |df| {ef:.3e}, max |dphi| {ep:.3e}", flush=True)
+    if storage == pkg.F64:
+        assert ef < 1e-13 and ep < 1e-13
+    else:
+        assert ef < 2e-7 and ep < (4e-7 if model == 2 else 2e-7)
+
+
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("storage", [pkg.F16, pkg.BF16, pkg.BF16_F16S])
 def test_largest_grid_16bit_invariants(storage):

@@ -333,20 +333,68 @@ LBM_HD void collide_cumulant27(CT* g, CT* ph, const Phys<CT>& p, CT* tau_out = n
   scalar_collision<LS, LES>(ph, chi, ux, uy, (jz + CT(0.5) * Fz) * irho, tau, p);
 }
 
-// ---- cumulant collision with general rates omega3..omega6 (PARAM false) or
-// the parametrised cumulant of Geier, Pasquali and Schoenherr (2017) that the
-// paper's VirtualFluids runs apply (Sec. 2.3; PARAM true, no LES):
-//   third order: the sums C_120 + C_102 (and permutations) relax with w_plus,
-//     the differences with w_minus, C_111 with w_111, each limited to
-//     w + (1 - w)|X| / (|X| + lambda) for its own quantity X;
-//   fourth order: rate 1 onto equilibria proportional to the velocity
-//     gradients, estimated from the pre-collision second-order cumulants at
-//     first Chapman-Enskog order (non-equilibrium part of C_ab =
-//     -(d_a u_b + d_b u_a) / (3 w), w = omega1 deviatoric, omega_bulk trace);
-//   fifth and sixth order: rate 1 towards 0.
-template <class LS, bool LES, typename CT, bool PARAM = false>
+// post-collision cumulants of orders 3..6 (of f / rho, zero mean)
+template <typename CT>
+struct HighCumulants {
+  CT c210, c201, c120, c021, c102, c012, c111;
+  CT c220, c202, c022, c211, c121, c112;
+  CT c221, c212, c122, c222;
+};
+
+// Post-collision populations from the relaxed second-order deviations
+// D = C - delta/3 (dxx..dyz) and the cumulants of orders 3..6: moments about
+// the post-collision mean from cumulants (zero mean), as deviations from the
+// rest values, then the inverse chimera transform.
+template <typename CT>
+LBM_HD void rebuild_from_cumulants(CT* g, CT drho, CT rho, CT dxx, CT dyy, CT dzz, CT dxy, CT dxz,
+                                   CT dyz, const HighCumulants<CT>& c, CT ux, CT uy, CT uz) {
+  const CT third = CT(1.0 / 3.0), ninth = CT(1.0 / 9.0);
+  CT m[27];
+  m[0] = drho;
+  m[1] = m[3] = m[9] = CT(0);
+  auto put = [&](int i, CT dev, double K) { m[i] = rho * dev + drho * CT(K); };
+  put(18, dxx, 1.0 / 3.0);
+  put(6, dyy, 1.0 / 3.0);
+  put(2, dzz, 1.0 / 3.0);
+  put(12, dxy, 0);
+  put(10, dxz, 0);
+  put(4, dyz, 0);
+  put(21, c.c210, 0);
+  put(19, c.c201, 0);
+  put(15, c.c120, 0);
+  put(7, c.c021, 0);
+  put(11, c.c102, 0);
+  put(5, c.c012, 0);
+  put(13, c.c111, 0);
+  put(24, c.c220 + (dxx + dyy) * third + dxx * dyy + CT(2) * dxy * dxy, 1.0 / 9.0);
+  put(20, c.c202 + (dxx + dzz) * third + dxx * dzz + CT(2) * dxz * dxz, 1.0 / 9.0);
+  put(8, c.c022 + (dyy + dzz) * third + dyy * dzz + CT(2) * dyz * dyz, 1.0 / 9.0);
+  put(22, c.c211 + (third + dxx) * dyz + CT(2) * dxy * dxz, 0);
+  put(16, c.c121 + (third + dyy) * dxz + CT(2) * dxy * dyz, 0);
+  put(14, c.c112 + (third + dzz) * dxy + CT(2) * dxz * dyz, 0);
+  put(25, c.c221 + (third + dxx) * c.c021 + (third + dyy) * c.c201 + CT(4) * dxy * c.c111 +
+              CT(2) * dxz * c.c120 + CT(2) * dyz * c.c210,
+      0);
+  put(23, c.c212 + (third + dxx) * c.c012 + (third + dzz) * c.c210 + CT(4) * dxz * c.c111 +
+              CT(2) * dxy * c.c102 + CT(2) * dyz * c.c201,
+      0);
+  put(17, c.c122 + (third + dyy) * c.c102 + (third + dzz) * c.c120 + CT(4) * dyz * c.c111 +
+              CT(2) * dxy * c.c012 + CT(2) * dxz * c.c021,
+      0);
+  const CT m222s =
+      c.c222 + (third + dxx) * c.c022 + (third + dyy) * c.c202 + (third + dzz) * c.c220 +
+      CT(4) * (dxy * c.c112 + dxz * c.c121 + dyz * c.c211) +
+      CT(2) * (c.c210 * c.c012 + c.c201 * c.c021 + c.c120 * c.c102) + CT(4) * c.c111 * c.c111 +
+      (dxx + dyy + dzz) * ninth + (dxx * dyy + dxx * dzz + dyy * dzz) * third + dxx * dyy * dzz +
+      CT(2) * ((third + dxx) * dyz * dyz + (third + dyy) * dxz * dxz + (third + dzz) * dxy * dxy) +
+      CT(8) * dxy * dxz * dyz;
+  put(26, m222s, 1.0 / 27.0);
+  inverse_chimera<CT>(m, ux, uy, uz, g);
+}
+
+// ---- cumulant collision with general rates omega3..omega6.
+template <class LS, bool LES, typename CT>
 LBM_HD void collide_cumulant27_general(CT* g, CT* ph, const Phys<CT>& p) {
-  static_assert(!(PARAM && LES), "the parametrised cumulant runs without the LES");
   CT drho = CT(0), jx = CT(0), jy = CT(0), jz = CT(0);
   static_for<0, 27>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
@@ -405,93 +453,114 @@ LBM_HD void collide_cumulant27_general(CT* g, CT* ph, const Phys<CT>& p) {
     tau = smagorinsky_tau(q2, p);
   }
   const CT a1 = CT(1) - CT(1) / tau;
-  CT C210, C201, C120, C021, C102, C012, C111;
-  CT C220, C202, C022, C211, C121, C112, C221, C212, C122, C222;
-  if constexpr (PARAM) {
-    // velocity gradients from the pre-collision second-order cumulants
-    // (dxx.. are C_ab - delta_ab / 3, so the trace deviation is their sum)
-    const CT w1 = CT(1) / tau;
-    const CT div = CT(-1.5) * p.omega2 * (dxx + dyy + dzz);
-    const CT dxy_d = CT(-1.5) * w1 * (dxx - dyy), dxz_d = CT(-1.5) * w1 * (dxx - dzz);
-    const CT dxux = (div + dxy_d + dxz_d) * third;
-    const CT dyuy = dxux - dxy_d, dzuz = dxux - dxz_d;
-    C220 = p.a4 * (dxux + dyuy);
-    C202 = p.a4 * (dxux + dzuz);
-    C022 = p.a4 * (dyuy + dzuz);
-    C112 = p.b4 * (CT(-3) * w1 * dxy);
-    C121 = p.b4 * (CT(-3) * w1 * dxz);
-    C211 = p.b4 * (CT(-3) * w1 * dyz);
-    // third order: 1 - limited rate = (1 - w)(1 - |X| / (|X| + lambda))
-    auto keep = [&](CT w, CT X) {
-      const CT a = X < CT(0) ? -X : X;
-      return (CT(1) - w) * (CT(1) - a / (a + p.lam));
-    };
-    auto pair = [&](CT a, CT b, CT& oa, CT& ob) {
-      CT s = a + b, d = a - b;
-      s *= keep(p.w_plus, s);
-      d *= keep(p.w_minus, d);
-      oa = CT(0.5) * (s + d);
-      ob = CT(0.5) * (s - d);
-    };
-    pair(m120, m102, C120, C102);
-    pair(m210, m012, C210, C012);
-    pair(m201, m021, C201, C021);
-    C111 = keep(p.w_111, m111) * m111;
-    C221 = C212 = C122 = C222 = CT(0);
-  } else {
-    const CT a3 = CT(1) - p.omega3, a4 = CT(1) - p.omega4, a5 = CT(1) - p.omega5,
-             a6 = CT(1) - p.omega6;
-    C210 = a3 * m210, C201 = a3 * m201, C120 = a3 * m120, C021 = a3 * m021;
-    C102 = a3 * m102, C012 = a3 * m012, C111 = a3 * m111;
-    C220 = a4 * c220, C202 = a4 * c202, C022 = a4 * c022;
-    C211 = a4 * c211, C121 = a4 * c121, C112 = a4 * c112;
-    C221 = a5 * c221, C212 = a5 * c212, C122 = a5 * c122;
-    C222 = a6 * c222;
-  }
   relax_second(a1, p.omega2, dxx, dyy, dzz, dxy, dxz, dyz);
-  // moments from cumulants (zero mean), deviations from rest
-  CT m[27];
-  m[0] = drho;
-  m[1] = m[3] = m[9] = CT(0);
-  auto put = [&](int i, CT dev, double K) { m[i] = rho * dev + drho * CT(K); };
-  put(18, dxx, 1.0 / 3.0);
-  put(6, dyy, 1.0 / 3.0);
-  put(2, dzz, 1.0 / 3.0);
-  put(12, dxy, 0);
-  put(10, dxz, 0);
-  put(4, dyz, 0);
-  put(21, C210, 0);
-  put(19, C201, 0);
-  put(15, C120, 0);
-  put(7, C021, 0);
-  put(11, C102, 0);
-  put(5, C012, 0);
-  put(13, C111, 0);
-  put(24, C220 + (dxx + dyy) * third + dxx * dyy + CT(2) * dxy * dxy, 1.0 / 9.0);
-  put(20, C202 + (dxx + dzz) * third + dxx * dzz + CT(2) * dxz * dxz, 1.0 / 9.0);
-  put(8, C022 + (dyy + dzz) * third + dyy * dzz + CT(2) * dyz * dyz, 1.0 / 9.0);
-  put(22, C211 + (third + dxx) * dyz + CT(2) * dxy * dxz, 0);
-  put(16, C121 + (third + dyy) * dxz + CT(2) * dxy * dyz, 0);
-  put(14, C112 + (third + dzz) * dxy + CT(2) * dxz * dyz, 0);
-  put(25, C221 + (third + dxx) * C021 + (third + dyy) * C201 + CT(4) * dxy * C111 +
-              CT(2) * dxz * C120 + CT(2) * dyz * C210,
-      0);
-  put(23, C212 + (third + dxx) * C012 + (third + dzz) * C210 + CT(4) * dxz * C111 +
-              CT(2) * dxy * C102 + CT(2) * dyz * C201,
-      0);
-  put(17, C122 + (third + dyy) * C102 + (third + dzz) * C120 + CT(4) * dyz * C111 +
-              CT(2) * dxy * C012 + CT(2) * dxz * C021,
-      0);
-  const CT m222s =
-      C222 + (third + dxx) * C022 + (third + dyy) * C202 + (third + dzz) * C220 +
-      CT(4) * (dxy * C112 + dxz * C121 + dyz * C211) +
-      CT(2) * (C210 * C012 + C201 * C021 + C120 * C102) + CT(4) * C111 * C111 +
-      (dxx + dyy + dzz) * ninth + (dxx * dyy + dxx * dzz + dyy * dzz) * third + dxx * dyy * dzz +
-      CT(2) * ((third + dxx) * dyz * dyz + (third + dyy) * dxz * dxz + (third + dzz) * dxy * dxy) +
-      CT(8) * dxy * dxz * dyz;
-  put(26, m222s, 1.0 / 27.0);
-  inverse_chimera<CT>(m, ux, uy, (jz + Fz) * irho, g);
+  const CT a3 = CT(1) - p.omega3, a4 = CT(1) - p.omega4, a5 = CT(1) - p.omega5,
+           a6 = CT(1) - p.omega6;
+  HighCumulants<CT> c;
+  c.c210 = a3 * m210, c.c201 = a3 * m201, c.c120 = a3 * m120, c.c021 = a3 * m021;
+  c.c102 = a3 * m102, c.c012 = a3 * m012, c.c111 = a3 * m111;
+  c.c220 = a4 * c220, c.c202 = a4 * c202, c.c022 = a4 * c022;
+  c.c211 = a4 * c211, c.c121 = a4 * c121, c.c112 = a4 * c112;
+  c.c221 = a5 * c221, c.c212 = a5 * c212, c.c122 = a5 * c122;
+  c.c222 = a6 * c222;
+  rebuild_from_cumulants<CT>(g, drho, rho, dxx, dyy, dzz, dxy, dxz, dyz, c, ux, uy, (jz + Fz) * irho);
   scalar_collision<LS, LES>(ph, chi, ux, uy, (jz + CT(0.5) * Fz) * irho, tau, p);
+}
+
+// ---- the parametrised cumulant of Geier, Pasquali and Schoenherr (2017) that
+// the paper's VirtualFluids runs apply (Sec. 2.3), without the LES:
+//   third order: the sums C_120 + C_102 (and permutations) relax with w_plus,
+//     the differences with w_minus, C_111 with w_111, each limited to
+//     w + (1 - w)|X| / (|X| + lambda) for its own quantity X;
+//   fourth order: rate 1 onto equilibria proportional to the velocity
+//     gradients, estimated from the pre-collision second-order cumulants at
+//     first Chapman-Enskog order (non-equilibrium part of C_ab =
+//     -(d_a u_b + d_b u_a) / (3 w), w = omega1 deviatoric, omega_bulk trace);
+//   fifth and sixth order: rate 1 towards 0.
+// Only the second- and third-order pre-collision cumulants are needed; they
+// come from raw sums of the deviations (the third-order raw moments of the
+// rest state vanish) instead of the full forward transform.
+template <class LS, typename CT>
+LBM_HD void collide_cumulant27_param(CT* g, CT* ph, const Phys<CT>& p) {
+  CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
+  flow_moments<Q27>(g, drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz);
+  // raw third-order sums r_abc = sum_q cx^a cy^b cz^c g_q
+  CT r120 = CT(0), r102 = CT(0), r210 = CT(0), r012 = CT(0), r201 = CT(0), r021 = CT(0),
+     r111 = CT(0);
+  static_for<0, 27>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int cx = Q27::cx[q], cy = Q27::cy[q], cz = Q27::cz[q];
+    const CT v = g[q];
+    if (cx && cy) r120 += cx > 0 ? v : -v;
+    if (cx && cz) r102 += cx > 0 ? v : -v;
+    if (cx && cy) r210 += cy > 0 ? v : -v;
+    if (cy && cz) r012 += cy > 0 ? v : -v;
+    if (cx && cz) r201 += cz > 0 ? v : -v;
+    if (cy && cz) r021 += cz > 0 ? v : -v;
+    if (cx && cy && cz) r111 += (cx * cy * cz) > 0 ? v : -v;
+  });
+  const CT chi = scalar_sum<LS>(ph);
+  const CT rho = CT(1) + drho;
+  const CT irho = CT(1) / rho;
+  const CT Fz = -p.g * chi;
+  const CT ux = jx * irho, uy = jy * irho, uz = jz * irho;  // pre-collision mean
+  const CT third = CT(1.0 / 3.0);
+  // second-order central deviations D = C - delta/3 (normalised by rho)
+  CT dxx = (pxx - drho * third) * irho - ux * ux;
+  CT dyy = (pyy - drho * third) * irho - uy * uy;
+  CT dzz = (pzz - drho * third) * irho - uz * uz;
+  CT dxy = pxy * irho - ux * uy;
+  CT dxz = pxz * irho - ux * uz;
+  CT dyz = pyz * irho - uy * uz;
+  // third-order central moments (= cumulants): E[(X-a)(Y-b)^2] =
+  // E[X Y^2] - a var(Y) - 2 b cov(X,Y) - a b^2, var(Y) = 1/3 + D_yy
+  const CT k120 = r120 * irho - ux * (third + dyy) - CT(2) * uy * dxy - ux * uy * uy;
+  const CT k102 = r102 * irho - ux * (third + dzz) - CT(2) * uz * dxz - ux * uz * uz;
+  const CT k210 = r210 * irho - uy * (third + dxx) - CT(2) * ux * dxy - uy * ux * ux;
+  const CT k012 = r012 * irho - uy * (third + dzz) - CT(2) * uz * dyz - uy * uz * uz;
+  const CT k201 = r201 * irho - uz * (third + dxx) - CT(2) * ux * dxz - uz * ux * ux;
+  const CT k021 = r021 * irho - uz * (third + dyy) - CT(2) * uy * dyz - uz * uy * uy;
+  const CT k111 = r111 * irho - ux * dyz - uy * dxz - uz * dxy - ux * uy * uz;
+  // velocity gradients from the pre-collision second-order cumulants
+  const CT w1 = CT(1) / p.tau0;
+  const CT div = CT(-1.5) * p.omega2 * (dxx + dyy + dzz);
+  const CT dxy_d = CT(-1.5) * w1 * (dxx - dyy), dxz_d = CT(-1.5) * w1 * (dxx - dzz);
+  const CT dxux = (div + dxy_d + dxz_d) * third;
+  const CT dyuy = dxux - dxy_d, dzuz = dxux - dxz_d;
+  HighCumulants<CT> c;
+  c.c220 = p.a4 * (dxux + dyuy);
+  c.c202 = p.a4 * (dxux + dzuz);
+  c.c022 = p.a4 * (dyuy + dzuz);
+  c.c112 = p.b4 * (CT(-3) * w1 * dxy);
+  c.c121 = p.b4 * (CT(-3) * w1 * dxz);
+  c.c211 = p.b4 * (CT(-3) * w1 * dyz);
+  c.c221 = c.c212 = c.c122 = c.c222 = CT(0);
+  // third order: 1 - limited rate = (1 - w)(1 - |X| / (|X| + lambda)); in
+  // FP32 the quotient takes the hardware reciprocal (1 ulp), which only
+  // scales a small third-order quantity; lambda = +inf gives 0 either way
+  auto keep = [&](CT w, CT X) {
+    const CT a = X < CT(0) ? -X : X;
+    CT q;
+    if constexpr (sizeof(CT) == 4)
+      q = a * __builtin_amdgcn_rcpf(a + p.lam);
+    else
+      q = a / (a + p.lam);
+    return (CT(1) - w) * (CT(1) - q);
+  };
+  auto pair = [&](CT a, CT b, CT& oa, CT& ob) {
+    CT s = a + b, d = a - b;
+    s *= keep(p.w_plus, s);
+    d *= keep(p.w_minus, d);
+    oa = CT(0.5) * (s + d);
+    ob = CT(0.5) * (s - d);
+  };
+  pair(k120, k102, c.c120, c.c102);
+  pair(k210, k012, c.c210, c.c012);
+  pair(k201, k021, c.c201, c.c021);
+  c.c111 = keep(p.w_111, k111) * k111;
+  relax_second(CT(1) - w1, p.omega2, dxx, dyy, dzz, dxy, dxz, dyz);
+  rebuild_from_cumulants<CT>(g, drho, rho, dxx, dyy, dzz, dxy, dxz, dyz, c, ux, uy, (jz + Fz) * irho);
+  scalar_collision<LS, false>(ph, chi, ux, uy, (jz + CT(0.5) * Fz) * irho, p.tau0, p);
 }
 
 // ---- D3Q19 BGK with Guo forcing (Eq. 21-26), Smagorinsky (Eq. 32-35),

@@ -128,7 +128,7 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
   for (int k = 0; k < NPT; ++k) {
     if constexpr (MODEL == 0 || MODEL == 2) {
       if constexpr (KIND == kCumParam)
-        collide_cumulant27_general<LS, false, CT, true>(fg[k], ph[k], p);
+        collide_cumulant27_param<LS, CT>(fg[k], ph[k], p);
       else if constexpr (KIND == kCumGeneral)
         collide_cumulant27_general<LS, LES, CT>(fg[k], ph[k], p);
       else

@@ -97,7 +97,8 @@ typedef struct {
   double g_prime;         /* reduced gravity, lattice units */
   double ub_lu;           /* > 0: U_b in lattice units, g' = ub_lu^2 / nz
                              (the paper's convention U_b = 0.03, Sec. 2.5) */
-  double cs_smag;         /* Smagorinsky constant C_s; 0 disables the LES */
+  double cs_smag;         /* Smagorinsky constant C_s; 0 disables the LES
+                             (convention: smag_paper_form below) */
   double sc_t;            /* turbulent Schmidt number */
   double omega_bulk;      /* cumulant trace (bulk) relaxation rate, (0, 2) */
   double omega3, omega4, omega5, omega6; /* cumulant rates of order 3..6 */
@@ -116,6 +117,10 @@ typedef struct {
    * rate w becomes w + (1 - w)|X| / (|X| + lambda) for its own third-order
    * quantity X (a cumulant of f / rho); 0 = no limiter; >= 0 */
   double limiter;
+  /* 1: the Smagorinsky closure as printed in Eq. 32, nu_T = C_s Delta^2 |S|
+   * (C_s to the first power; the paper's C_s = 0.03 equals the standard
+   * form's 0.173); 0: the standard nu_T = (C_s Delta)^2 |S|. Delta = 1. */
+  int32_t smag_paper_form;
 } lbm_config;
 
 /* Derived lattice-unit parameters (Sec. 2.5, Eq. 25, 30). */

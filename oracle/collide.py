@@ -50,15 +50,18 @@ def smagorinsky_tau(pi_neq, rho, P, cs_smag):
     Q = Pi:Pi. This is the root of tau^2 - tau0 tau - 3 C_s^2 |S| tau = 0 with
     |S| tau = 3 sqrt(2 Q) / (2 rho) (strain from the stress, S = -Pi/(2 rho cs^2
     tau)), i.e. nu_T = (C_s)^2 |S| and tau_f = tau0 + 3 nu_T (Eq. 25, 32-34).
-    The square root of Q uses a zero subgradient at Q = 0.
+    The square root of Q uses a zero subgradient at Q = 0. With the
+    configuration's smag_paper_form the closure is the one printed in Eq. 32,
+    nu_T = C_s |S| (Delta = 1), so C_s enters where C_s^2 stands above.
     """
     if cs_smag == 0.0:
         return torch.full_like(rho, P.tau0)
+    cs_term = cs_smag if P.cfg.smag_paper_form else cs_smag ** 2
     Q = (pi_neq * pi_neq).sum((0, 1))
     pos = Q > 0
     sq = torch.where(pos, torch.sqrt(torch.where(pos, Q, torch.ones_like(Q))),
                      torch.zeros_like(Q))
-    return 0.5 * (P.tau0 + torch.sqrt(P.tau0 ** 2 + 18.0 * math.sqrt(2.0) * cs_smag ** 2 * sq / rho))
+    return 0.5 * (P.tau0 + torch.sqrt(P.tau0 ** 2 + 18.0 * math.sqrt(2.0) * cs_term * sq / rho))
 
 
 def scalar_tau(tau_f, P, sc_t):

@@ -44,6 +44,9 @@ class Config:
     # third-order relaxation, 0 = no limiter
     parametrized: bool = False
     limiter: float = 0.0
+    # Smagorinsky closure as printed in Eq. 32, nu_T = C_s Delta^2 |S| (C_s
+    # enters to the first power); default: the standard (C_s Delta)^2 |S|
+    smag_paper_form: bool = False
     # oracle-only switches for the closed-form checks (the product has walls)
     periodic_x: bool = False
     periodic_z: bool = False

@@ -48,7 +48,8 @@ class c_config(ctypes.Structure):
                 ("ub_lu", ctypes.c_double), ("cs_smag", ctypes.c_double), ("sc_t", ctypes.c_double),
                 ("omega_bulk", ctypes.c_double), ("omega3", ctypes.c_double),
                 ("omega4", ctypes.c_double), ("omega5", ctypes.c_double), ("omega6", ctypes.c_double),
-                ("parametrized", ctypes.c_int32), ("limiter", ctypes.c_double)]
+                ("parametrized", ctypes.c_int32), ("limiter", ctypes.c_double),
+                ("smag_paper_form", ctypes.c_int32)]
 
 
 class c_params(ctypes.Structure):
@@ -136,6 +137,7 @@ class Config:
     omega6: float = 1.0
     parametrized: bool = False     # parametrised cumulant (third-order rates from omega1)
     limiter: float = 0.0           # third-order limiter lambda; 0 = none
+    smag_paper_form: bool = False  # nu_T = C_s |S| as printed (else (C_s)^2 |S|)
 
     def c(self):
         s = c_config()

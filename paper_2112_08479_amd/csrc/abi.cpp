@@ -141,6 +141,8 @@ int validate(const lbm_config* c, lbm_params* out) {
   p.w_plus = p.w_minus = p.w_111 = p.coef_a = p.coef_b = 0.0;
   if (c->parametrized != 0 && c->parametrized != 1)
     return fail(LBM_EINVAL, "parametrized must be 0 or 1");
+  if (c->smag_paper_form != 0 && c->smag_paper_form != 1)
+    return fail(LBM_EINVAL, "smag_paper_form must be 0 or 1");
   if (!(c->limiter >= 0) || std::isinf(c->limiter))
     return fail(LBM_EINVAL, "limiter must be finite and >= 0");
   if (c->parametrized) {

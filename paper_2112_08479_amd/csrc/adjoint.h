@@ -2,7 +2,8 @@
 // in collide.h, written out by hand: given the pre-collision deviations g,
 // scalar populations ph and the adjoints mg, mp of the post-collision values,
 // return the adjoints gb, pb of the inputs and accumulate the adjoints of the
-// parameters c_les = 18 sqrt(2) C_s^2 and inv_sct = 1 / Sc_T.
+// parameters c_les = 18 sqrt(2) C_s^2 (18 sqrt(2) C_s for the Smagorinsky
+// closure as printed) and inv_sct = 1 / Sc_T.
 //
 // Each function first recomputes the forward quantities it needs, in the
 // order of the forward code, then runs the chain rule backwards through them.

@@ -61,7 +61,7 @@ __device__ __forceinline__ int64_t rpull_offset(const Grid& g, int base, int x, 
 
 struct AdjStep {
   double a0, a1;        // F_w seed coefficients at z = 0 and z = 1 (0 when not seeded)
-  double dcs_dc;        // d c_les / d C_s = 36 sqrt(2) C_s
+  double dcs_dc;        // d c_les / d C_s: 36 sqrt(2) C_s, or 18 sqrt(2) in the printed form
   double disct_dsct;    // d (1/Sc_T) / d Sc_T = -1 / Sc_T^2
   double* gpart;        // per-block accumulators (2 doubles per block)
   double* dchi0;        // non-null: write dJ/dchi0 (the step m = 0)
@@ -368,7 +368,7 @@ static Phys<CT> aphys(const lbm_handle* h) {
   r.g = (CT)q.g_prime;
   r.tau0 = (CT)q.tau0;
   r.tau_phi0 = (CT)q.tau_phi0;
-  r.c_les = (CT)(18.0 * sqrt(2.0) * c.cs_smag * c.cs_smag);
+  r.c_les = (CT)(18.0 * sqrt(2.0) * (c.smag_paper_form ? c.cs_smag : c.cs_smag * c.cs_smag));
   r.d0 = (CT)q.d0;
   r.inv_sct = (CT)(1.0 / c.sc_t);
   r.inv_cs2phi = (CT)(1.0 / q.cs2_phi);
@@ -406,7 +406,7 @@ hipError_t launch_adjoint_step(lbm_handle* h, const void* state, const void* lam
   AdjStep a;
   a.a0 = a0;
   a.a1 = a1;
-  a.dcs_dc = 36.0 * sqrt(2.0) * h->cfg.cs_smag;
+  a.dcs_dc = h->cfg.smag_paper_form ? 18.0 * sqrt(2.0) : 36.0 * sqrt(2.0) * h->cfg.cs_smag;
   a.disct_dsct = -1.0 / (h->cfg.sc_t * h->cfg.sc_t);
   a.gpart = gpart;
   a.dchi0 = dchi0;

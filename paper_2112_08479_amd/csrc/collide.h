@@ -32,7 +32,7 @@ struct Phys {
   CT g;           // g'
   CT tau0;        // 3 nu0 + 1/2
   CT tau_phi0;    // 1/2 + D0 / cs_phi^2
-  CT c_les;       // 18 sqrt(2) C_s^2
+  CT c_les;       // 18 sqrt(2) C_s^2 (18 sqrt(2) C_s for the closure as printed)
   CT d0;          // nu0 / Sc
   CT inv_sct;     // 1 / Sc_T
   CT inv_cs2phi;  // 1 / cs_phi^2

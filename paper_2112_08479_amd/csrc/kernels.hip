@@ -557,7 +557,8 @@ static Phys<CT> phys_of(const lbm_handle* h) {
   r.g = (CT)p.g_prime;
   r.tau0 = (CT)p.tau0;
   r.tau_phi0 = (CT)p.tau_phi0;
-  r.c_les = (CT)(18.0 * sqrt(2.0) * c.cs_smag * c.cs_smag);
+  // 18 sqrt(2) C_s^2 (standard closure) or 18 sqrt(2) C_s (as printed in Eq. 32)
+  r.c_les = (CT)(18.0 * sqrt(2.0) * (c.smag_paper_form ? c.cs_smag : c.cs_smag * c.cs_smag));
   r.d0 = (CT)p.d0;
   r.inv_sct = (CT)(1.0 / c.sc_t);
   r.inv_cs2phi = (CT)(1.0 / p.cs2_phi);

@@ -9,7 +9,8 @@ from oracle.params import Config as OConfig
 from oracle.params import derive
 
 ORACLE_KEYS = ("nx", "ny", "nz", "model", "re_b", "sc", "g_prime", "ub_lu", "cs_smag", "sc_t",
-               "omega_bulk", "omega3", "omega4", "omega5", "omega6", "parametrized", "limiter")
+               "omega_bulk", "omega3", "omega4", "omega5", "omega6", "parametrized", "limiter",
+               "smag_paper_form")
 
 
 def both(storage, **kw):

@@ -82,6 +82,7 @@ BAD = [
     (dict(nx=8, ny=8, nz=16, parametrized=True, limiter=-1e-3), "limiter"),
     (dict(nx=8, ny=8, nz=16, parametrized=True, limiter=float("inf")), "limiter"),
     (dict(nx=8, ny=8, nz=16, parametrized=2), "parametrized"),
+    (dict(nx=8, ny=8, nz=16, smag_paper_form=3), "smag_paper_form"),
     # A and B are singular where the shear and bulk rates coincide
     (dict(nx=8, ny=8, nz=16, re_b=1000.0, g_prime=1e-4, parametrized=True,
           omega_bulk=1.0 / (3.0 * (1e-4 * 16) ** 0.5 * 16 / 1000.0 + 0.5)), "singular"),

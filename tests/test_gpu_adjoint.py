@@ -44,7 +44,10 @@ def _gpu_grad(kw, storage, chi0, n, k, w_front=1.0, w_fw=1.0):
 
 TINY = [dict(nx=64, ny=4, nz=8, model=0, re_b=1000.0, cs_smag=0.1, sc_t=1.0, g_prime=1e-4),
         dict(nx=64, ny=4, nz=8, model=1, re_b=1000.0, cs_smag=0.1, sc_t=1.0, g_prime=1e-4),
-        dict(nx=64, ny=4, nz=8, model=2, re_b=1000.0, cs_smag=0.1, sc_t=1.0, g_prime=1e-4)]
+        dict(nx=64, ny=4, nz=8, model=2, re_b=1000.0, cs_smag=0.1, sc_t=1.0, g_prime=1e-4),
+        # the Smagorinsky closure as printed (C_s to the first power), the paper's C_s
+        dict(nx=64, ny=4, nz=8, model=0, re_b=1000.0, cs_smag=0.03, sc_t=1.0, g_prime=1e-4,
+             smag_paper_form=True)]
 _ref = {}
 
 
@@ -59,7 +62,7 @@ def _oracle_ref(i):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("i", [0, 1, 2], ids=["cumulant", "bgk", "cumulant_fcm"])
+@pytest.mark.parametrize("i", [0, 1, 2, 3], ids=["cumulant", "bgk", "cumulant_fcm", "cumulant_printed_smag"])
 @pytest.mark.parametrize("storage,tol", [(pkg.F64, 1e-8), (pkg.F32, 2e-3)], ids=["f64", "f32"])
 def test_adjoint_matches_oracle_autograd(i, storage, tol):
     chi0, (J, gcs, gsct, gchi) = _oracle_ref(i)

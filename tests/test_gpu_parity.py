@@ -102,6 +102,28 @@ def test_one_step_from_random_state(model, cs, rates, storage):
     assert np.abs(phi1 - ophi).max() < tol * _scalar_factor(model)
 
 
+@pytest.mark.parametrize("model", [0, 1, 2])
+@pytest.mark.parametrize("storage", [pkg.F64, pkg.F32])
+def test_one_step_with_the_printed_smagorinsky_form(model, storage):
+    """nu_T = C_s |S| as printed in Eq. 32, with the paper's C_s = 0.03."""
+    shape = (5, 3, 300)
+    kw = dict(nx=shape[2], ny=shape[1], nz=shape[0], model=model, re_b=2000.0, g_prime=1e-3,
+              cs_smag=0.03, smag_paper_form=True)
+    cfg, P = both(storage, **kw)
+    f, phi = inputs.near_rest_state(P.flow.Q, P.scal.Q, shape, P.flow.w.numpy(), P.scal.w.numpy(), 21,
+                                    eps=1e-2)
+    lat = pkg.Lattice(cfg)
+    lat.set_populations(f, phi)
+    f0, phi0 = lat.get_populations()
+    lat.step(1)
+    f1, phi1 = lat.get_populations()
+    lat.close()
+    of, ophi = olbm.step(torch.from_numpy(f0), torch.from_numpy(phi0), P)
+    tol = 1e-13 if storage == pkg.F64 else 2e-7
+    assert np.abs(f1 - of.numpy()).max() < tol
+    assert np.abs(phi1 - ophi.numpy()).max() < tol * _scalar_factor(model)
+
+
 @pytest.mark.parametrize("model,cs,rates", CASES)
 @pytest.mark.parametrize("storage,mant,mant_s", [(pkg.F16, 10, 10), (pkg.BF16, 7, 7),
                                                  (pkg.BF16_F16S, 7, 10)])

@@ -101,6 +101,27 @@ def test_smagorinsky_uniform_shear():
     assert abs(float(got[0]) - tau) < 1e-15
 
 
+def test_smagorinsky_printed_form():
+    """The closure as printed in Eq. 32 (nu_T = C_s |S|, Delta = 1): uniform
+    shear gives nu_T = C_s |s|, and the form equals the standard one at
+    C_s' = sqrt(C_s)."""
+    import dataclasses
+    P = _P(re_b=30000.0)
+    Pp = dataclasses.replace(P, cfg=dataclasses.replace(P.cfg, smag_paper_form=True))
+    s, cs, rho = 2e-3, 0.03, 1.0
+    tau = P.tau0 + 3 * cs * abs(s)
+    pi = torch.zeros(3, 3, 1, dtype=torch.float64)
+    pi[0, 2] = pi[2, 0] = -2 * rho * (1 / 3) * tau * (s / 2)
+    got = C.smagorinsky_tau(pi, torch.tensor([rho], dtype=torch.float64), Pp, cs)
+    assert abs(float(got[0]) - tau) < 1e-15
+    rng = np.random.default_rng(8)
+    A = torch.from_numpy(rng.standard_normal((3, 3, 20)) * 1e-3)
+    pi = A + A.transpose(0, 1)
+    r = torch.from_numpy(rng.uniform(0.95, 1.05, 20))
+    assert torch.allclose(C.smagorinsky_tau(pi, r, Pp, cs), C.smagorinsky_tau(pi, r, P, cs ** 0.5),
+                          rtol=1e-15, atol=0)
+
+
 def test_les_off_is_bitwise_the_plain_path():
     f, phi = inputs.near_rest_state(27, 7, (1, 1, 40), L.D3Q27.w.numpy(), L.D3Q7.w.numpy(), 3, eps=1e-2)
     f, phi = torch.from_numpy(f.reshape(27, 40)), torch.from_numpy(phi.reshape(7, 40))

@@ -211,7 +211,9 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, 
   L.gpart = off;
   off += align256((size_t)ablocks * 2 * sizeof(double));
   L.fwpart = off;
-  off += align256((size_t)n_steps * fblocks * 2 * sizeof(double));  // one slot set per step
+  // one slot set per step, plus one that takes the unused sums of step 0 and
+  // of the recomputed steps
+  off += align256((size_t)(n_steps + 1) * fblocks * 2 * sizeof(double));
   L.small = off;
   off += 256;
   L.total = off;
@@ -265,18 +267,25 @@ int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_fro
   HIPCHECK(lbm::launch_zero(h, gpart, 2 * (int64_t)nblk));
   HIPCHECK(lbm::launch_zero(h, small, 32));
   // forward with checkpoints; the wall-layer sums of F_w(m), m = 1..n, go to
-  // one slot set per step and are reduced once, in fixed order, at the end
+  // one slot set per step (slot m - 1) and are reduced once, in fixed order,
+  // at the end. Step m -> m + 1 gathers state m and writes F_w(m) itself; the
+  // final state's F_w(n) takes the separate wall-layer kernel. Every forward
+  // and recomputed step runs the same kernel (step 0 and the recomputation
+  // write into the spare slot set), so the recomputed states are bitwise the
+  // checkpointed trajectory's whatever the checkpoint interval.
   const int fwb = lbm::fw_blocks(h);
+  double* fw_spare = fwpart + 2 * (size_t)fwb * n_steps;
   for (int64_t s = 0; s < L.nseg; ++s) {
     HIPCHECK(hipMemcpyAsync(ckpt(s), h->buf[h->cur], sbytes, hipMemcpyDeviceToDevice, h->stream));
     const int64_t steps = std::min<int64_t>(k_ckpt, n_steps - s * k_ckpt);
     for (int64_t i = 0; i < steps; ++i) {
-      HIPCHECK(lbm::launch_step(h, h->buf[h->cur], h->buf[h->cur ^ 1]));
+      double* fw = h->step >= 1 ? fwpart + 2 * (size_t)fwb * (h->step - 1) : fw_spare;
+      HIPCHECK(lbm::launch_step(h, h->buf[h->cur], h->buf[h->cur ^ 1], fw));
       h->cur ^= 1;
-      HIPCHECK(lbm::launch_fw_layers(h, h->buf[h->cur], fwpart + 2 * (size_t)fwb * h->step));
       h->step += 1;
     }
   }
+  HIPCHECK(lbm::launch_fw_layers(h, h->buf[h->cur], fwpart + 2 * (size_t)fwb * (n_steps - 1)));
   HIPCHECK(lbm::launch_fw_reduce(h, fwpart, n_steps * fwb, small));
   // final state: front and its seed, lambda(n)
   HIPCHECK(lbm::launch_diag(h, h->dres));
@@ -291,7 +300,8 @@ int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_fro
     const int64_t m0 = s * k_ckpt;
     const int64_t e = std::min<int64_t>(m0 + k_ckpt, n_steps);
     HIPCHECK(hipMemcpyAsync(traj(0), ckpt(s), sbytes, hipMemcpyDeviceToDevice, h->stream));
-    for (int64_t i = 0; i + 1 < e - m0; ++i) HIPCHECK(lbm::launch_step(h, traj(i), traj(i + 1)));
+    for (int64_t i = 0; i + 1 < e - m0; ++i)
+      HIPCHECK(lbm::launch_step(h, traj(i), traj(i + 1), fw_spare));
     for (int64_t m = e - 1; m >= m0; --m) {
       const bool seed = m >= 1;
       HIPCHECK(lbm::launch_adjoint_step(h, traj(m - m0), lam_next, lam_out, seed ? a0 : 0.0,

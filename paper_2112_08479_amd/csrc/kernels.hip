@@ -110,20 +110,53 @@ __device__ __forceinline__ int block_order(int b, int nblocks, int nbx) {
 enum { kCumFast = 0, kCumGeneral = 1, kCumParam = 2 };
 
 // one tile: NPT * blockDim.x consecutive nodes of one row; KIND: kCumFast
-// (omega3..omega6 = 1), kCumGeneral (given rates), kCumParam (parametrised)
-template <int MODEL, typename ST, typename SS, typename CT, bool LES, int KIND, int NPT>
+// (omega3..omega6 = 1), kCumGeneral (given rates), kCumParam (parametrised).
+// FW (the adjoint's forward pass): the tiles of the wall layers z = 0, 1 also
+// write the x-velocity sums of their x-blocks that F_w (Eq. 62, 64) needs for
+// the state they gather, as the separate wall-layer kernel does: per x-block
+// the wave sum of u_x = j_x / rho (FP64, populations in order) into
+// fwp[2 b + z], with b = xb + nxb (y + ny z), and 0 into the other slot.
+template <int MODEL, typename ST, typename SS, typename CT, bool LES, int KIND, int NPT,
+          bool FW = false>
 __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __restrict__ dst,
-                                          const Grid& g, const Phys<CT>& p, int nbx, int b) {
+                                          const Grid& g, const Phys<CT>& p, int nbx, int b,
+                                          double* __restrict__ fwp) {
   using LF = typename ModelT<MODEL>::LF;
   using LS = typename ModelT<MODEL>::LS;
   const int row = b / nbx;
   const int x0 = (b - row * nbx) * (int)blockDim.x * NPT;
-  if (x0 + (int)threadIdx.x >= g.nx) return;  // lanes with no node at all
+  // lanes with no node at all; the wave sums of FW need every lane of a wave
+  if (!FW && x0 + (int)threadIdx.x >= g.nx) return;
   const int y = row % g.ny, z = row / g.ny;
   constexpr int QT = LF::Q + LS::Q;
   const TileLanes<QT, NPT> t = tile_lanes<QT, NPT>(g, x0, (int)threadIdx.x, (int)blockDim.x);
   CT fg[NPT][LF::Q], ph[NPT][LS::Q];
   gather_rows<LF, LS, NPT, ST, CT, SS>(src, g, t, y, z, fg, ph);
+  if constexpr (FW) {
+    if (z < 2) {  // uniform per block
+      const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+#pragma unroll
+      for (int k = 0; k < NPT; ++k) {
+        double v = 0.0;
+        if (t.x[k] < g.nx) {
+          double drho = 0.0, jx = 0.0;
+          static_for<0, LF::Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            drho += (double)fg[k][q];
+            if (LF::cx[q]) jx += LF::cx[q] * (double)fg[k][q];
+          });
+          v = jx / (1.0 + drho);
+        }
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        const int xb = ((x0 + k * (int)blockDim.x) >> kXBShift) + wave;
+        if (lane == 0 && xb < g.nxb) {
+          const int64_t fb = xb + (int64_t)g.nxb * (y + (int64_t)g.ny * z);
+          fwp[2 * fb] = z == 0 ? v : 0.0;
+          fwp[2 * fb + 1] = z == 0 ? 0.0 : v;
+        }
+      }
+    }
+  }
 #pragma unroll
   for (int k = 0; k < NPT; ++k) {
     if constexpr (MODEL == 0 || MODEL == 2) {
@@ -144,7 +177,7 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
     ST* pa = drow + a * kXB;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-      if (k == 0 || t.x[k] < g.nx) {
+      if ((k == 0 && !FW) || t.x[k] < g.nx) {
         if constexpr (a < LF::Q)
           store_val(&pa[t.own[k]], Conv<ST, CT>::store(fg[k][a]));
         else
@@ -159,16 +192,18 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
 #define LBM_STEP_WAVES 0
 #endif
 
-template <int MODEL, typename ST, typename SS, typename CT, bool LES, int KIND, int NPT>
+template <int MODEL, typename ST, typename SS, typename CT, bool LES, int KIND, int NPT,
+          bool FW = false>
 __global__ __launch_bounds__(kBlock, LBM_STEP_WAVES) void k_step(const ST* __restrict__ src, ST* __restrict__ dst,
-                                                 Grid g, Phys<CT> p, int nbx, int ntiles) {
+                                                 Grid g, Phys<CT> p, int nbx, int ntiles,
+                                                 double* __restrict__ fwp) {
 #if LBM_PERSIST
   for (int b = blockIdx.x; b < ntiles; b += gridDim.x)
-    step_tile<MODEL, ST, SS, CT, LES, KIND, NPT>(src, dst, g, p, nbx, b);
+    step_tile<MODEL, ST, SS, CT, LES, KIND, NPT, FW>(src, dst, g, p, nbx, b, fwp);
 #else
   (void)ntiles;
-  step_tile<MODEL, ST, SS, CT, LES, KIND, NPT>(src, dst, g, p, nbx,
-                                               block_order(blockIdx.x, gridDim.x, nbx));
+  step_tile<MODEL, ST, SS, CT, LES, KIND, NPT, FW>(src, dst, g, p, nbx,
+                                                   block_order(blockIdx.x, gridDim.x, nbx), fwp);
 #endif
 }
 
@@ -608,7 +643,8 @@ static int cumulant_kind(const lbm_handle* h) {
 }
 
 template <int M, typename ST, typename SS, typename CT, int NPT>
-static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src, void* dst) {
+static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src, void* dst,
+                                  double* fw) {
   const bool les = h->cfg.cs_smag > 0.0;
   const int per_thread_x = (g.nx + NPT - 1) / NPT;  // x-extent in threads if one block
   const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
@@ -622,24 +658,36 @@ static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src,
   const Phys<CT> p = phys_of<CT>(h);
   const ST* s = static_cast<const ST*>(src);
   ST* d = static_cast<ST*>(dst);
+  if (fw) {  // the adjoint's forward pass: FP32 / FP64 storage, rates fixed at 1
+    if constexpr (std::is_same<ST, CT>::value && std::is_same<SS, ST>::value) {
+      if (M != 1 && cumulant_kind(h) != kCumFast) return hipErrorInvalidValue;
+      if (les)
+        hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, fw);
+      else
+        hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, fw);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if constexpr (M == 1) {  // BGK: one collision kind
     if (les)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
     else
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
   } else {
     // the parametrised kind never has the LES (rejected when the handle is made)
     const int kind = cumulant_kind(h);
     if (les && kind == kCumGeneral)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
     else if (les)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
     else if (kind == kCumParam)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumParam, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumParam, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
     else if (kind == kCumGeneral)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
     else
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
   }
   return hipGetLastError();
 }
@@ -652,7 +700,7 @@ static bool few_waves(const lbm_handle* h, int npt) {
   return waves < (int64_t)16 * h->cu_count;
 }
 
-hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
+hipError_t launch_step(lbm_handle* h, const void* src, void* dst, double* fw) {
   const Grid g = grid_of(h);
   return with_model(h, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
@@ -662,9 +710,9 @@ hipError_t launch_step(lbm_handle* h, const void* src, void* dst) {
       using CT = decltype(ct);
       constexpr int NPT = nodes_per_thread<M, ST>();
       if constexpr (NPT > 1) {
-        if (few_waves(h, NPT)) return launch_step_npt<M, ST, SS, CT, 1>(h, g, src, dst);
+        if (few_waves(h, NPT)) return launch_step_npt<M, ST, SS, CT, 1>(h, g, src, dst, fw);
       }
-      return launch_step_npt<M, ST, SS, CT, NPT>(h, g, src, dst);
+      return launch_step_npt<M, ST, SS, CT, NPT>(h, g, src, dst, fw);
     });
   });
 }

@@ -61,7 +61,10 @@ constexpr int nodes_per_thread() {
 constexpr int kDiagSlots = 8;  // partial sums per diagnostic block
 
 // kernels.hip
-hipError_t launch_step(lbm_handle* h, const void* src, void* dst);
+// one step src -> dst; fw (the adjoint's forward pass, FP32 / FP64 storage):
+// also the wall-layer sums of F_w of the gathered state into
+// fw[2 fw_blocks], as launch_fw_layers writes them
+hipError_t launch_step(lbm_handle* h, const void* src, void* dst, double* fw = nullptr);
 hipError_t launch_init_lock(lbm_handle* h, double lock_fraction, double amp, uint64_t seed);
 hipError_t launch_init_field(lbm_handle* h, const double* chi0);
 hipError_t launch_moments(lbm_handle* h, int dtype, void* rho, void* ux, void* uy, void* uz,

@@ -110,16 +110,11 @@ struct Conv<bf16_t, float> {
     uint32_t u = (uint32_t)v.bits << 16;
     return __uint_as_float(u);
   }
-  // round to nearest even on the 16 dropped bits; NaN stays NaN
+  // round to nearest even (gfx950 converts in hardware, v_cvt_pk_bf16_f32);
+  // NaN stays NaN
   static LBM_HD bf16_t store(float v) {
-    uint32_t u = __float_as_uint(v);
     bf16_t r;
-    if ((u & 0x7fffffffu) > 0x7f800000u) {
-      r.bits = (uint16_t)((u >> 16) | 0x40u);
-    } else {
-      u += 0x7fffu + ((u >> 16) & 1u);
-      r.bits = (uint16_t)(u >> 16);
-    }
+    r.bits = __builtin_bit_cast(uint16_t, (__bf16)v);
     return r;
   }
 };

@@ -241,12 +241,15 @@ int lbm_set_populations(lbm_handle* h, const double* host_f, const double* host_
  * which must be a fresh initialisation (step 0). The forward pass keeps a
  * checkpoint every k_ckpt steps; the reverse pass recomputes each segment and
  * runs the hand-written adjoint of the gather with bounce-back and of the
- * local collision (Eq. 17, 21-35, 37-51, 54-58). Outputs: *J_out, *dJ_dcs (C_s),
+ * local collision (Eq. 17, 21-35, 37-51, 54-58; Sec. 2.3 for the
+ * parametrised cumulant). Outputs: *J_out, *dJ_dcs (C_s),
  * *dJ_dsct (Sc_T) as host doubles and dJ/dchi0 (nx*ny*nz doubles, device;
  * chi0 enters through phi(0) = w_phi chi0). Non-smooth points: zero
  * subgradient of sqrt(Q) at Q = 0; the front uses the active column i* and
- * the first depth maximum. Requires omega3..omega6 = 1 and parametrized = 0
- * for the cumulant models and storage LBM_F32 or LBM_F64 (LBM_EINVAL
+ * the first depth maximum. The cumulant models need omega3..omega6 = 1 or
+ * the parametrised mode (its limiter differentiated as
+ * d/dX [X (1 - w)(1 - |X|/(|X| + lambda))] = (1 - w)(1 - q)^2,
+ * q = |X|/(|X| + lambda)); storage LBM_F32 or LBM_F64 (LBM_EINVAL
  * otherwise); LBM_ESTATE if the
  * handle is not at step 0. adj_ws: device scratch of
  * lbm_adjoint_workspace_bytes(cfg, n, k_ckpt) bytes (LBM_ENOMEM if smaller).

@@ -226,8 +226,6 @@ int adjoint_supported(const lbm_config* c) {
   if (c->model != LBM_BGK19_SMAG_Q6 &&
       (c->omega3 != 1.0 || c->omega4 != 1.0 || c->omega5 != 1.0 || c->omega6 != 1.0))
     return fail(LBM_EINVAL, "the cumulant adjoint needs omega3..omega6 = 1");
-  if (c->parametrized)
-    return fail(LBM_EINVAL, "the adjoint does not cover the parametrised cumulant");
   return LBM_OK;
 }
 }  // namespace

@@ -385,6 +385,269 @@ LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, const CT* mg, const CT* mp
   flow_moments_vjp<Q27, CT>(bdrho, bjx, bjy, bjz, bpxx, bpyy, bpzz, bpxy, bpxz, bpyz, gb);
 }
 
+// ---- parametrised cumulant D3Q27 (no LES) + scalar lattice LS: the
+// derivative of collide_cumulant27_param. The limited third-order map
+// X -> X (1 - w)(1 - |X| / (|X| + lambda)) has the derivative
+// (1 - w)(1 - q)^2, q = |X| / (|X| + lambda), which is smooth at X = 0.
+template <class LS, typename CT>
+LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, const CT* mg, const CT* mp,
+                                 const Phys<CT>& p, CT* gb, CT* pb, CT& b_isct) {
+  // ---- forward recompute (as collide_cumulant27_param)
+  CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
+  flow_moments<Q27>(g, drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz);
+  CT r120 = CT(0), r102 = CT(0), r210 = CT(0), r012 = CT(0), r201 = CT(0), r021 = CT(0),
+     r111 = CT(0);
+  static_for<0, 27>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int cx = Q27::cx[q], cy = Q27::cy[q], cz = Q27::cz[q];
+    const CT v = g[q];
+    if (cx && cy) r120 += cx > 0 ? v : -v;
+    if (cx && cz) r102 += cx > 0 ? v : -v;
+    if (cx && cy) r210 += cy > 0 ? v : -v;
+    if (cy && cz) r012 += cy > 0 ? v : -v;
+    if (cx && cz) r201 += cz > 0 ? v : -v;
+    if (cy && cz) r021 += cz > 0 ? v : -v;
+    if (cx && cy && cz) r111 += (cx * cy * cz) > 0 ? v : -v;
+  });
+  const CT chi = scalar_sum<LS>(ph);
+  const CT rho = CT(1) + drho;
+  const CT ir = CT(1) / rho;
+  const CT Fz = -p.g * chi;
+  const CT ux = jx * ir, uy = jy * ir, uz = jz * ir;
+  const CT third = CT(1.0 / 3.0), ninth = CT(1.0 / 9.0);
+  const CT dxx = (pxx - drho * third) * ir - ux * ux;
+  const CT dyy = (pyy - drho * third) * ir - uy * uy;
+  const CT dzz = (pzz - drho * third) * ir - uz * uz;
+  const CT dxy = pxy * ir - ux * uy;
+  const CT dxz = pxz * ir - ux * uz;
+  const CT dyz = pyz * ir - uy * uz;
+  const CT k120 = r120 * ir - ux * (third + dyy) - CT(2) * uy * dxy - ux * uy * uy;
+  const CT k102 = r102 * ir - ux * (third + dzz) - CT(2) * uz * dxz - ux * uz * uz;
+  const CT k210 = r210 * ir - uy * (third + dxx) - CT(2) * ux * dxy - uy * ux * ux;
+  const CT k012 = r012 * ir - uy * (third + dzz) - CT(2) * uz * dyz - uy * uz * uz;
+  const CT k201 = r201 * ir - uz * (third + dxx) - CT(2) * ux * dxz - uz * ux * ux;
+  const CT k021 = r021 * ir - uz * (third + dyy) - CT(2) * uy * dyz - uz * uy * uy;
+  const CT k111 = r111 * ir - ux * dyz - uy * dxz - uz * dxy - ux * uy * uz;
+  const CT w1 = CT(1) / p.tau0;
+  const CT div = CT(-1.5) * p.omega2 * (dxx + dyy + dzz);
+  const CT dxy_d = CT(-1.5) * w1 * (dxx - dyy), dxz_d = CT(-1.5) * w1 * (dxx - dzz);
+  const CT dxux = (div + dxy_d + dxz_d) * third;
+  const CT dyuy = dxux - dxy_d, dzuz = dxux - dxz_d;
+  const CT C220 = p.a4 * (dxux + dyuy), C202 = p.a4 * (dxux + dzuz), C022 = p.a4 * (dyuy + dzuz);
+  const CT C112 = p.b4 * (CT(-3) * w1 * dxy), C121 = p.b4 * (CT(-3) * w1 * dxz),
+           C211 = p.b4 * (CT(-3) * w1 * dyz);
+  // third-order pairs: keep factors and q of the sums and differences
+  CT qs[3], qd[3], ks[3], kd[3], sv[3], dv[3];
+  const CT ka[3] = {k120, k210, k201}, kb[3] = {k102, k012, k021};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    sv[i] = ka[i] + kb[i];
+    dv[i] = ka[i] - kb[i];
+    ks[i] = third_order_keep(p.w_plus, sv[i], p.lam, qs[i]);
+    kd[i] = third_order_keep(p.w_minus, dv[i], p.lam, qd[i]);
+  }
+  CT q111;
+  const CT k3 = third_order_keep(p.w_111, k111, p.lam, q111);
+  const CT C120 = CT(0.5) * (sv[0] * ks[0] + dv[0] * kd[0]), C102 = CT(0.5) * (sv[0] * ks[0] - dv[0] * kd[0]);
+  const CT C210 = CT(0.5) * (sv[1] * ks[1] + dv[1] * kd[1]), C012 = CT(0.5) * (sv[1] * ks[1] - dv[1] * kd[1]);
+  const CT C201 = CT(0.5) * (sv[2] * ks[2] + dv[2] * kd[2]), C021 = CT(0.5) * (sv[2] * ks[2] - dv[2] * kd[2]);
+  const CT C111 = k3 * k111;
+  const CT a1 = CT(1) - w1;
+  CT exx = dxx, eyy = dyy, ezz = dzz, exy = dxy, exz = dxz, eyz = dyz;
+  relax_second(a1, p.omega2, exx, eyy, ezz, exy, exz, eyz);
+  const CT W24 = (exx + eyy) * third + exx * eyy + CT(2) * exy * exy;
+  const CT W20 = (exx + ezz) * third + exx * ezz + CT(2) * exz * exz;
+  const CT W8 = (eyy + ezz) * third + eyy * ezz + CT(2) * eyz * eyz;
+  const CT W22 = (third + exx) * eyz + CT(2) * exy * exz;
+  const CT W16 = (third + eyy) * exz + CT(2) * exy * eyz;
+  const CT W14 = (third + ezz) * exy + CT(2) * exz * eyz;
+  const CT W26 = (exx + eyy + ezz) * ninth + (exx * eyy + exx * ezz + eyy * ezz) * third +
+                 exx * eyy * ezz +
+                 CT(2) * ((third + exx) * eyz * eyz + (third + eyy) * exz * exz +
+                          (third + ezz) * exy * exy) +
+                 CT(8) * exy * exz * eyz;
+  // moments about the post-collision mean, as deviations from rest (the
+  // same as rebuild_from_cumulants with orders 5 and 6 at 0)
+  CT dev[27];
+  static_for<0, 27>([&](auto ic) { dev[decltype(ic)::value] = CT(0); });
+  dev[18] = exx, dev[6] = eyy, dev[2] = ezz, dev[12] = exy, dev[10] = exz, dev[4] = eyz;
+  dev[21] = C210, dev[19] = C201, dev[15] = C120, dev[7] = C021, dev[11] = C102, dev[5] = C012;
+  dev[13] = C111;
+  dev[24] = C220 + W24, dev[20] = C202 + W20, dev[8] = C022 + W8;
+  dev[22] = C211 + W22, dev[16] = C121 + W16, dev[14] = C112 + W14;
+  dev[25] = (third + exx) * C021 + (third + eyy) * C201 + CT(4) * exy * C111 + CT(2) * exz * C120 +
+            CT(2) * eyz * C210;
+  dev[23] = (third + exx) * C012 + (third + ezz) * C210 + CT(4) * exz * C111 + CT(2) * exy * C102 +
+            CT(2) * eyz * C201;
+  dev[17] = (third + eyy) * C102 + (third + ezz) * C120 + CT(4) * eyz * C111 + CT(2) * exy * C012 +
+            CT(2) * exz * C021;
+  dev[26] = (third + exx) * C022 + (third + eyy) * C202 + (third + ezz) * C220 +
+            CT(4) * (exy * C112 + exz * C121 + eyz * C211) +
+            CT(2) * (C210 * C012 + C201 * C021 + C120 * C102) + CT(4) * C111 * C111 + W26;
+  CT m[27];
+  m[0] = drho;
+  m[1] = m[3] = m[9] = CT(0);
+  static_for<1, 27>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    if constexpr (i != 1 && i != 3 && i != 9) m[i] = rho * dev[i] + drho * CT(rest_moment(i));
+  });
+  const CT vz = (jz + Fz) * ir;
+  const CT uzs = (jz + CT(0.5) * Fz) * ir;
+
+  // ---- reverse
+  CT bchi = CT(0), bux = CT(0), buy = CT(0), buz = CT(0), btau = CT(0), buzs = CT(0);
+  scalar_collision_vjp<LS, false, CT>(ph, chi, ux, uy, uzs, p.tau0, p, mp, pb, bchi, bux, buy, buzs,
+                                      btau, b_isct);
+  CT mb[27];
+  CT bvz = CT(0);
+  inverse_chimera_vjp<CT>(m, ux, uy, vz, mg, mb, bux, buy, bvz);
+  CT brho = CT(0), bdrho = mb[0];
+  CT r[27];
+  static_for<1, 27>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    if constexpr (i != 1 && i != 3 && i != 9) {
+      brho += mb[i] * dev[i];
+      bdrho += mb[i] * CT(rest_moment(i));
+      r[i] = mb[i] * rho;
+    }
+  });
+  // cumulants of orders 3 and 4
+  const CT bC210 = r[21] + r[25] * CT(2) * eyz + r[23] * (third + ezz) + r[26] * CT(2) * C012;
+  const CT bC201 = r[19] + r[25] * (third + eyy) + r[23] * CT(2) * eyz + r[26] * CT(2) * C021;
+  const CT bC120 = r[15] + r[25] * CT(2) * exz + r[17] * (third + ezz) + r[26] * CT(2) * C102;
+  const CT bC021 = r[7] + r[25] * (third + exx) + r[17] * CT(2) * exz + r[26] * CT(2) * C201;
+  const CT bC102 = r[11] + r[23] * CT(2) * exy + r[17] * (third + eyy) + r[26] * CT(2) * C120;
+  const CT bC012 = r[5] + r[23] * (third + exx) + r[17] * CT(2) * exy + r[26] * CT(2) * C210;
+  const CT bC111 = r[13] + CT(4) * (r[25] * exy + r[23] * exz + r[17] * eyz) + r[26] * CT(8) * C111;
+  const CT bC220 = r[24] + r[26] * (third + ezz), bC202 = r[20] + r[26] * (third + eyy),
+           bC022 = r[8] + r[26] * (third + exx);
+  const CT bC211 = r[22] + r[26] * CT(4) * eyz, bC121 = r[16] + r[26] * CT(4) * exz,
+           bC112 = r[14] + r[26] * CT(4) * exy;
+  // relaxed second order: from the Wick parts and the products with C
+  CT bexx = r[18] + r[25] * C021 + r[23] * C012 + r[26] * C022;
+  CT beyy = r[6] + r[25] * C201 + r[17] * C102 + r[26] * C202;
+  CT bezz = r[2] + r[23] * C210 + r[17] * C120 + r[26] * C220;
+  CT bexy = r[12] + r[25] * CT(4) * C111 + r[23] * CT(2) * C102 + r[17] * CT(2) * C012 +
+            r[26] * CT(4) * C112;
+  CT bexz = r[10] + r[25] * CT(2) * C120 + r[23] * CT(4) * C111 + r[17] * CT(2) * C021 +
+            r[26] * CT(4) * C121;
+  CT beyz = r[4] + r[25] * CT(2) * C210 + r[23] * CT(2) * C201 + r[17] * CT(4) * C111 +
+            r[26] * CT(4) * C211;
+  {
+    const CT r24 = r[24], r20 = r[20], r8 = r[8];
+    bexx += r24 * (third + eyy) + r20 * (third + ezz);
+    beyy += r24 * (third + exx) + r8 * (third + ezz);
+    bezz += r20 * (third + exx) + r8 * (third + eyy);
+    bexy += r24 * CT(4) * exy;
+    bexz += r20 * CT(4) * exz;
+    beyz += r8 * CT(4) * eyz;
+    const CT r22 = r[22], r16 = r[16], r14 = r[14];
+    bexx += r22 * eyz;
+    beyz += r22 * (third + exx);
+    bexy += r22 * CT(2) * exz;
+    bexz += r22 * CT(2) * exy;
+    beyy += r16 * exz;
+    bexz += r16 * (third + eyy);
+    bexy += r16 * CT(2) * eyz;
+    beyz += r16 * CT(2) * exy;
+    bezz += r14 * exy;
+    bexy += r14 * (third + ezz);
+    bexz += r14 * CT(2) * eyz;
+    beyz += r14 * CT(2) * exz;
+    const CT r26 = r[26];
+    bexx += r26 * (ninth + (eyy + ezz) * third + eyy * ezz + CT(2) * eyz * eyz);
+    beyy += r26 * (ninth + (exx + ezz) * third + exx * ezz + CT(2) * exz * exz);
+    bezz += r26 * (ninth + (exx + eyy) * third + exx * eyy + CT(2) * exy * exy);
+    bexy += r26 * (CT(4) * (third + ezz) * exy + CT(8) * exz * eyz);
+    bexz += r26 * (CT(4) * (third + eyy) * exz + CT(8) * exy * eyz);
+    beyz += r26 * (CT(4) * (third + exx) * eyz + CT(8) * exy * exz);
+  }
+  // relaxation of the second order (a1 fixed: no LES)
+  const CT bT3 = ((CT(1) - p.omega2) - a1) * (bexx + beyy + bezz);
+  CT bdxx = a1 * bexx + bT3 * third, bdyy = a1 * beyy + bT3 * third, bdzz = a1 * bezz + bT3 * third;
+  CT bdxy = a1 * bexy, bdxz = a1 * bexz, bdyz = a1 * beyz;
+  // fourth-order equilibria through the gradient estimates
+  {
+    const CT bdxux = p.a4 * (bC220 + bC202), bdyuy = p.a4 * (bC220 + bC022),
+             bdzuz = p.a4 * (bC202 + bC022);
+    const CT bsum = bdxux + bdyuy + bdzuz;         // adjoint of dxux through all three
+    const CT bdxy_d = bsum * third - bdyuy, bdxz_d = bsum * third - bdzuz;
+    const CT bdiv = bsum * third;
+    bdxx += CT(-1.5) * p.omega2 * bdiv + CT(-1.5) * w1 * (bdxy_d + bdxz_d);
+    bdyy += CT(-1.5) * p.omega2 * bdiv + CT(1.5) * w1 * bdxy_d;
+    bdzz += CT(-1.5) * p.omega2 * bdiv + CT(1.5) * w1 * bdxz_d;
+    bdxy += CT(-3) * w1 * p.b4 * bC112;
+    bdxz += CT(-3) * w1 * p.b4 * bC121;
+    bdyz += CT(-3) * w1 * p.b4 * bC211;
+  }
+  // third order through the limited pairs
+  CT bka[3], bkb[3];
+  const CT bCa[3] = {bC120, bC210, bC201}, bCb[3] = {bC102, bC012, bC021};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const CT bsp = CT(0.5) * (bCa[i] + bCb[i]), bdp = CT(0.5) * (bCa[i] - bCb[i]);
+    const CT bs = bsp * (CT(1) - p.w_plus) * (CT(1) - qs[i]) * (CT(1) - qs[i]);
+    const CT bd = bdp * (CT(1) - p.w_minus) * (CT(1) - qd[i]) * (CT(1) - qd[i]);
+    bka[i] = bs + bd;
+    bkb[i] = bs - bd;
+  }
+  const CT bk111 = bC111 * (CT(1) - p.w_111) * (CT(1) - q111) * (CT(1) - q111);
+  // third-order central moments from the raw sums
+  CT bir = CT(0);
+  const CT bk120 = bka[0], bk102 = bkb[0], bk210 = bka[1], bk012 = bkb[1], bk201 = bka[2],
+           bk021 = bkb[2];
+  const CT br120 = bk120 * ir, br102 = bk102 * ir, br210 = bk210 * ir, br012 = bk012 * ir,
+           br201 = bk201 * ir, br021 = bk021 * ir, br111 = bk111 * ir;
+  bir += bk120 * r120 + bk102 * r102 + bk210 * r210 + bk012 * r012 + bk201 * r201 + bk021 * r021 +
+         bk111 * r111;
+  bux -= bk120 * (third + dyy + uy * uy) + bk102 * (third + dzz + uz * uz) +
+         bk210 * CT(2) * (dxy + uy * ux) + bk201 * CT(2) * (dxz + uz * ux) + bk111 * (dyz + uy * uz);
+  buy -= bk210 * (third + dxx + ux * ux) + bk012 * (third + dzz + uz * uz) +
+         bk120 * CT(2) * (dxy + ux * uy) + bk021 * CT(2) * (dyz + uz * uy) + bk111 * (dxz + ux * uz);
+  buz -= bk201 * (third + dxx + ux * ux) + bk021 * (third + dyy + uy * uy) +
+         bk102 * CT(2) * (dxz + ux * uz) + bk012 * CT(2) * (dyz + uy * uz) + bk111 * (dxy + ux * uy);
+  bdxx -= bk210 * uy + bk201 * uz;
+  bdyy -= bk120 * ux + bk021 * uz;
+  bdzz -= bk102 * ux + bk012 * uy;
+  bdxy -= CT(2) * (bk120 * uy + bk210 * ux) + bk111 * uz;
+  bdxz -= CT(2) * (bk102 * uz + bk201 * ux) + bk111 * uy;
+  bdyz -= CT(2) * (bk012 * uz + bk021 * uy) + bk111 * ux;
+  // D from raw moments
+  CT bpxx = bdxx * ir, bpyy = bdyy * ir, bpzz = bdzz * ir;
+  CT bpxy = bdxy * ir, bpxz = bdxz * ir, bpyz = bdyz * ir;
+  bdrho -= (bdxx + bdyy + bdzz) * ir * third;
+  bir += bdxx * (pxx - drho * third) + bdyy * (pyy - drho * third) + bdzz * (pzz - drho * third) +
+         bdxy * pxy + bdxz * pxz + bdyz * pyz;
+  bux -= CT(2) * ux * bdxx + uy * bdxy + uz * bdxz;
+  buy -= CT(2) * uy * bdyy + ux * bdxy + uz * bdyz;
+  buz -= CT(2) * uz * bdzz + ux * bdxz + uy * bdyz;
+  // velocities
+  CT bjx = bux * ir, bjy = buy * ir, bjz = buz * ir;
+  bir += bux * jx + buy * jy + buz * jz;
+  bjz += bvz * ir + buzs * ir;
+  const CT bFz = bvz * ir + buzs * ir * CT(0.5);
+  bir += bvz * (jz + Fz) + buzs * (jz + CT(0.5) * Fz);
+  bchi += -p.g * bFz;
+  brho += -bir * ir * ir;
+  bdrho += brho;
+  static_for<0, LS::Q>([&](auto qc) { pb[decltype(qc)::value] += bchi; });
+  static_for<0, 27>([&](auto qc) { gb[decltype(qc)::value] = CT(0); });
+  flow_moments_vjp<Q27, CT>(bdrho, bjx, bjy, bjz, bpxx, bpyy, bpzz, bpxy, bpxz, bpyz, gb);
+  static_for<0, 27>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int cx = Q27::cx[q], cy = Q27::cy[q], cz = Q27::cz[q];
+    CT t = CT(0);
+    if (cx && cy) t += cx > 0 ? br120 : -br120;
+    if (cx && cz) t += cx > 0 ? br102 : -br102;
+    if (cx && cy) t += cy > 0 ? br210 : -br210;
+    if (cy && cz) t += cy > 0 ? br012 : -br012;
+    if (cx && cz) t += cz > 0 ? br201 : -br201;
+    if (cy && cz) t += cz > 0 ? br021 : -br021;
+    if (cx && cy && cz) t += (cx * cy * cz) > 0 ? br111 : -br111;
+    gb[q] += t;
+  });
+}
+
 // ---- BGK D3Q19 + Guo + Smagorinsky, D3Q6 scalar
 template <bool LES, typename CT>
 LBM_HD void vjp_bgk_q19_q6(const CT* g, const CT* ph, const CT* mg, const CT* mp, const Phys<CT>& p,

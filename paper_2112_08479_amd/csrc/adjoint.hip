@@ -67,7 +67,7 @@ struct AdjStep {
   double* dchi0;        // non-null: write dJ/dchi0 (the step m = 0)
 };
 
-template <int MODEL, typename ST, typename CT, bool LES>
+template <int MODEL, typename ST, typename CT, bool LES, bool PARAM = false>
 __global__ __launch_bounds__(kBlock) void k_adjoint_step(const ST* __restrict__ state,
                                                          const CT* __restrict__ lam_next,
                                                          CT* __restrict__ lam_out, Grid g,
@@ -92,7 +92,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(const ST* __restrict__ 
       mp[q] = lam_next[rpull_offset<LS, q, LF::Q + LS::Q>(g, LF::Q, x, y, z)];
     });
     CT bc = CT(0), bi = CT(0);
-    if constexpr (MODEL == 0 || MODEL == 2)
+    if constexpr ((MODEL == 0 || MODEL == 2) && PARAM)
+      vjp_cumulant27_param<LS, CT>(fg, ph, mg, mp, p, gb, pb, bi);
+    else if constexpr (MODEL == 0 || MODEL == 2)
       vjp_cumulant27<LS, LES, CT>(fg, ph, mg, mp, p, gb, pb, bc, bi);
     else
       vjp_bgk_q19_q6<LES, CT>(fg, ph, mg, mp, p, gb, pb, bc, bi);
@@ -377,9 +379,14 @@ static Phys<CT> aphys(const lbm_handle* h) {
   r.omega4 = (CT)c.omega4;
   r.omega5 = (CT)c.omega5;
   r.omega6 = (CT)c.omega6;
-  // the adjoint runs only with the fixed rates (parametrised mode is rejected)
-  r.w_plus = r.w_minus = r.w_111 = r.a4 = r.b4 = (CT)0;
-  r.lam = (CT)INFINITY;
+  // parametrised cumulant (as for the forward step)
+  const double h4 = q.tau0 - 0.5;  // 1/omega1 - 1/2
+  r.w_plus = (CT)q.w_plus;
+  r.w_minus = (CT)q.w_minus;
+  r.w_111 = (CT)q.w_111;
+  r.a4 = (CT)(-2.0 / 3.0 * h4 * q.coef_a);
+  r.b4 = (CT)(-1.0 / 3.0 * h4 * q.coef_b);
+  r.lam = c.limiter > 0.0 ? (CT)c.limiter : (CT)INFINITY;
   return r;
 }
 
@@ -416,7 +423,11 @@ hipError_t launch_adjoint_step(lbm_handle* h, const void* state, const void* lam
     using CT = decltype(ct);
     using ST = CT;
     const Phys<CT> p = aphys<CT>(h);
-    if (les)
+    if (M != 1 && h->cfg.parametrized)  // never with the LES
+      hipLaunchKernelGGL((k_adjoint_step<M, ST, CT, false, true>), dim3(blocks), dim3(bx), 0, h->stream,
+                         static_cast<const ST*>(state), static_cast<const CT*>(lam_next),
+                         static_cast<CT*>(lam_out), g, p, a, nbx);
+    else if (les)
       hipLaunchKernelGGL((k_adjoint_step<M, ST, CT, true>), dim3(blocks), dim3(bx), 0, h->stream,
                          static_cast<const ST*>(state), static_cast<const CT*>(lam_next),
                          static_cast<CT*>(lam_out), g, p, a, nbx);

@@ -46,6 +46,8 @@ struct Phys {
 // one-dimensional rest central moments k_c and weights w(c), c = -1, 0, 1
 LBM_HD constexpr double k1d(int a) { return a == 0 ? 1.0 : (a == 1 ? 0.0 : 1.0 / 3.0); }
 LBM_HD constexpr double w1d(int i) { return i == 1 ? 2.0 / 3.0 : 1.0 / 6.0; }
+// rest value of the central moment m[9a + 3b + c]: k_a k_b k_c
+LBM_HD constexpr double rest_moment(int i) { return k1d(i / 9) * k1d((i / 3) % 3) * k1d(i % 3); }
 
 // values t(-1), t(0), t(+1) of a triple whose rest values are K (1/6, 2/3, 1/6)
 // -> central moments of order 0, 1, 2 about u, minus their rest values K (1, 0, 1/3)
@@ -333,6 +335,21 @@ LBM_HD void collide_cumulant27(CT* g, CT* ph, const Phys<CT>& p, CT* tau_out = n
   scalar_collision<LS, LES>(ph, chi, ux, uy, (jz + CT(0.5) * Fz) * irho, tau, p);
 }
 
+// Third-order limiter of the parametrised cumulant: 1 - (limited rate) for
+// the quantity X, (1 - w)(1 - q) with q = |X| / (|X| + lambda) (also
+// returned); lambda = +inf gives q = 0. In FP32 the quotient takes the
+// hardware reciprocal (1 ulp), which only scales a small third-order
+// quantity.
+template <typename CT>
+LBM_HD CT third_order_keep(CT w, CT X, CT lam, CT& q) {
+  const CT a = X < CT(0) ? -X : X;
+  if constexpr (sizeof(CT) == 4)
+    q = a * __builtin_amdgcn_rcpf(a + lam);
+  else
+    q = a / (a + lam);
+  return (CT(1) - w) * (CT(1) - q);
+}
+
 // post-collision cumulants of orders 3..6 (of f / rho, zero mean)
 template <typename CT>
 struct HighCumulants {
@@ -535,17 +552,10 @@ LBM_HD void collide_cumulant27_param(CT* g, CT* ph, const Phys<CT>& p) {
   c.c121 = p.b4 * (CT(-3) * w1 * dxz);
   c.c211 = p.b4 * (CT(-3) * w1 * dyz);
   c.c221 = c.c212 = c.c122 = c.c222 = CT(0);
-  // third order: 1 - limited rate = (1 - w)(1 - |X| / (|X| + lambda)); in
-  // FP32 the quotient takes the hardware reciprocal (1 ulp), which only
-  // scales a small third-order quantity; lambda = +inf gives 0 either way
+  // third order, limited
   auto keep = [&](CT w, CT X) {
-    const CT a = X < CT(0) ? -X : X;
     CT q;
-    if constexpr (sizeof(CT) == 4)
-      q = a * __builtin_amdgcn_rcpf(a + p.lam);
-    else
-      q = a / (a + p.lam);
-    return (CT(1) - w) * (CT(1) - q);
+    return third_order_keep(w, X, p.lam, q);
   };
   auto pair = [&](CT a, CT b, CT& oa, CT& ob) {
     CT s = a + b, d = a - b;

@@ -658,9 +658,16 @@ static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src,
   const Phys<CT> p = phys_of<CT>(h);
   const ST* s = static_cast<const ST*>(src);
   ST* d = static_cast<ST*>(dst);
-  if (fw) {  // the adjoint's forward pass: FP32 / FP64 storage, rates fixed at 1
+  if (fw) {  // the adjoint's forward pass: FP32 / FP64 storage
     if constexpr (std::is_same<ST, CT>::value && std::is_same<SS, ST>::value) {
-      if (M != 1 && cumulant_kind(h) != kCumFast) return hipErrorInvalidValue;
+      const int kind = M == 1 ? kCumFast : cumulant_kind(h);
+      if (kind == kCumGeneral) return hipErrorInvalidValue;
+      if constexpr (M != 1) {
+        if (kind == kCumParam) {
+          hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumParam, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, fw);
+          return hipGetLastError();
+        }
+      }
       if (les)
         hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, fw);
       else

@@ -1,8 +1,9 @@
 """The hand-written adjoint (lbm_adjoint_run) against the oracle.
 
 * 64 x 4 x 8, 200 steps, checkpoints every 50: J, dJ/dC_s, dJ/dSc_T and the
-  field dJ/dchi0 against torch autograd through the FP64 oracle, every model;
-  FP64 storage to 1e-8 (relative to the largest entry), FP32 to 2e-3.
+  field dJ/dchi0 against torch autograd through the FP64 oracle, every model,
+  the Smagorinsky closure as printed, and the parametrised cumulant with the
+  limiter; FP64 storage to 1e-8 (relative to the largest entry), FP32 to 2e-3.
 * 128 x 8 x 16, 500 steps (cumulant, Re_b 1000, C_s 0.1, Sc_T 1): against the
   oracle's FP64 central differences stored in tests/golden (written by
   tests/golden/make_adjoint_fd.py, which calls only the oracle): FP64 to 1e-5,
@@ -47,7 +48,12 @@ TINY = [dict(nx=64, ny=4, nz=8, model=0, re_b=1000.0, cs_smag=0.1, sc_t=1.0, g_p
         dict(nx=64, ny=4, nz=8, model=2, re_b=1000.0, cs_smag=0.1, sc_t=1.0, g_prime=1e-4),
         # the Smagorinsky closure as printed (C_s to the first power), the paper's C_s
         dict(nx=64, ny=4, nz=8, model=0, re_b=1000.0, cs_smag=0.03, sc_t=1.0, g_prime=1e-4,
-             smag_paper_form=True)]
+             smag_paper_form=True),
+        # the parametrised cumulant without the LES, limiter active at most nodes
+        dict(nx=64, ny=4, nz=8, model=2, re_b=1000.0, cs_smag=0.0, sc_t=1.0, g_prime=1e-4,
+             parametrized=True, limiter=1e-4),
+        dict(nx=64, ny=4, nz=8, model=0, re_b=1000.0, cs_smag=0.0, sc_t=1.0, g_prime=1e-4,
+             parametrized=True, limiter=1e-2)]
 _ref = {}
 
 
@@ -62,7 +68,8 @@ def _oracle_ref(i):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("i", [0, 1, 2, 3], ids=["cumulant", "bgk", "cumulant_fcm", "cumulant_printed_smag"])
+@pytest.mark.parametrize("i", [0, 1, 2, 3, 4, 5], ids=["cumulant", "bgk", "cumulant_fcm", "cumulant_printed_smag",
+                                               "parametrised_fcm", "parametrised_cumulant"])
 @pytest.mark.parametrize("storage,tol", [(pkg.F64, 1e-8), (pkg.F32, 2e-3)], ids=["f64", "f32"])
 def test_adjoint_matches_oracle_autograd(i, storage, tol):
     chi0, (J, gcs, gsct, gchi) = _oracle_ref(i)

@@ -53,17 +53,22 @@ VARIANTS = ["cumulant27_q7_2048x128x256_fp16", "cumulant27_q7_2048x128x256_bf16"
             "cumulant27param_fcm27_2048x128x256_fp16"]
 
 
-def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0):
+def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0, param=False):
     """Differentiation form: one lbm_adjoint_run (forward with checkpoints,
     recompute, hand-written adjoint) of the lock exchange, FP32, Re_b = 1000,
-    C_s = 0.1, Sc_T = 1. MNUPS counts the n_steps node updates of the
+    C_s = 0.1, Sc_T = 1 (param: the parametrised cumulant with limiter 1e-2
+    and no LES, Re_b = 30000). MNUPS counts the n_steps node updates of the
     differentiated run; the algorithmic bytes per node update are a forward
     (2 Q 4 B), its recompute (2 Q 4 B) and the reverse step (3 Q 4 B), Q the
     populations per node."""
     import torch
 
     import paper_2112_08479_amd as pkg
-    cfg = pkg.Config(nx, ny, nz, model=model, storage=pkg.F32, re_b=1000.0, cs_smag=0.1, sc_t=1.0)
+    if param:
+        cfg = pkg.Config(nx, ny, nz, model=model, storage=pkg.F32, re_b=30000.0, parametrized=True,
+                         limiter=1e-2)
+    else:
+        cfg = pkg.Config(nx, ny, nz, model=model, storage=pkg.F32, re_b=1000.0, cs_smag=0.1, sc_t=1.0)
     lat = pkg.Lattice(cfg)
     lat.init_lock_exchange(0.125, 1e-3, 0)
     torch.cuda.synchronize()
@@ -77,6 +82,8 @@ def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0):
     bpn = 2 * q * 4 + 2 * q * 4 + 3 * q * 4
     mnups = n * n_steps / dt / 1e6
     name = ["cumulant27_q7", "bgk19_smag_q6", "cumulant27_fcm27"][model]
+    if param:
+        name = name.replace("cumulant27", "cumulant27param")
     return {"workload": f"adjoint_{name}_{nx}x{ny}x{nz}_fp32_{n_steps}steps_k{k_ckpt}",
             "nodes": n, "steps": n_steps, "seconds": dt, "MNUPS": mnups,
             "bytes_per_node_update": bpn, "GB_per_s": mnups * 1e6 * bpn / 1e9,
@@ -261,7 +268,8 @@ def main():
             print(json.dumps({"progress": "variant", **r}), file=sys.stderr, flush=True)
             variants.append(r)
         for kw in (dict(), dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25),
-                   dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25, model=2)):
+                   dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25, model=2),
+                   dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25, model=2, param=True)):
             r = measure_adjoint(**kw)
             print(json.dumps({"progress": "adjoint", **r}), file=sys.stderr, flush=True)
             variants.append(r)

@@ -66,5 +66,5 @@ def gradient(cfg, chi0, n_end, w_front=1.0, w_fw=1.0, k_ckpt=100, lock_fraction=
     J = _run(chi, cs, sct, P, n_end, w_front, w_fw, k_ckpt, lock_fraction)
     gcs, gsct, gchi = torch.autograd.grad(J, (cs, sct, chi), allow_unused=True)
     z = torch.zeros((), dtype=torch.float64)
-    return (float(J), float(gcs if gcs is not None else z), float(gsct if gsct is not None else z),
+    return (float(J.detach()), float(gcs if gcs is not None else z), float(gsct if gsct is not None else z),
             gchi if gchi is not None else torch.zeros_like(chi0))

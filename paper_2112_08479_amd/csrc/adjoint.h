@@ -395,20 +395,10 @@ LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, const CT* mg, const 
   // ---- forward recompute (as collide_cumulant27_param)
   CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
   flow_moments<Q27>(g, drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz);
-  CT r120 = CT(0), r102 = CT(0), r210 = CT(0), r012 = CT(0), r201 = CT(0), r021 = CT(0),
-     r111 = CT(0);
-  static_for<0, 27>([&](auto qc) {
-    constexpr int q = decltype(qc)::value;
-    constexpr int cx = Q27::cx[q], cy = Q27::cy[q], cz = Q27::cz[q];
-    const CT v = g[q];
-    if (cx && cy) r120 += cx > 0 ? v : -v;
-    if (cx && cz) r102 += cx > 0 ? v : -v;
-    if (cx && cy) r210 += cy > 0 ? v : -v;
-    if (cy && cz) r012 += cy > 0 ? v : -v;
-    if (cx && cz) r201 += cz > 0 ? v : -v;
-    if (cy && cz) r021 += cz > 0 ? v : -v;
-    if (cx && cy && cz) r111 += (cx * cy * cz) > 0 ? v : -v;
-  });
+  CT r3[7];
+  third_raw_sums<CT>(g, r3);
+  const CT r120 = r3[0], r102 = r3[1], r210 = r3[2], r012 = r3[3], r201 = r3[4], r021 = r3[5],
+           r111 = r3[6];
   const CT chi = scalar_sum<LS>(ph);
   const CT rho = CT(1) + drho;
   const CT ir = CT(1) / rho;
@@ -421,13 +411,10 @@ LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, const CT* mg, const 
   const CT dxy = pxy * ir - ux * uy;
   const CT dxz = pxz * ir - ux * uz;
   const CT dyz = pyz * ir - uy * uz;
-  const CT k120 = r120 * ir - ux * (third + dyy) - CT(2) * uy * dxy - ux * uy * uy;
-  const CT k102 = r102 * ir - ux * (third + dzz) - CT(2) * uz * dxz - ux * uz * uz;
-  const CT k210 = r210 * ir - uy * (third + dxx) - CT(2) * ux * dxy - uy * ux * ux;
-  const CT k012 = r012 * ir - uy * (third + dzz) - CT(2) * uz * dyz - uy * uz * uz;
-  const CT k201 = r201 * ir - uz * (third + dxx) - CT(2) * ux * dxz - uz * ux * ux;
-  const CT k021 = r021 * ir - uz * (third + dyy) - CT(2) * uy * dyz - uz * uy * uy;
-  const CT k111 = r111 * ir - ux * dyz - uy * dxz - uz * dxy - ux * uy * uz;
+  CT kc[7];
+  third_central<CT>(r3, ir, ux, uy, uz, dxx, dyy, dzz, dxy, dxz, dyz, kc);
+  const CT k120 = kc[0], k102 = kc[1], k210 = kc[2], k012 = kc[3], k201 = kc[4], k021 = kc[5],
+           k111 = kc[6];
   const CT w1 = CT(1) / p.tau0;
   const CT div = CT(-1.5) * p.omega2 * (dxx + dyy + dzz);
   const CT dxy_d = CT(-1.5) * w1 * (dxx - dyy), dxz_d = CT(-1.5) * w1 * (dxx - dzz);

@@ -350,6 +350,43 @@ LBM_HD CT third_order_keep(CT w, CT X, CT lam, CT& q) {
   return (CT(1) - w) * (CT(1) - q);
 }
 
+// Third-order central moments (= cumulants) of f / rho from the deviations g,
+// for the parametrised cumulant: raw sums r_abc = sum_q cx^a cy^b cz^c g_q
+// (the rest state's vanish), then E[(X-a)(Y-b)^2] = E[X Y^2] - a var(Y)
+// - 2 b cov(X,Y) - a b^2 with var(Y) = 1/3 + D_yy, and
+// E[(X-a)(Y-b)(Z-c)] = E[XYZ] - a cov(Y,Z) - b cov(X,Z) - c cov(X,Y) - abc.
+// Order of r and k: 120, 102, 210, 012, 201, 021, 111.
+template <typename CT>
+LBM_HD void third_raw_sums(const CT* g, CT (&r)[7]) {
+#pragma unroll
+  for (int i = 0; i < 7; ++i) r[i] = CT(0);
+  static_for<0, 27>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr int cx = Q27::cx[q], cy = Q27::cy[q], cz = Q27::cz[q];
+    const CT v = g[q];
+    if (cx && cy) r[0] += cx > 0 ? v : -v;
+    if (cx && cz) r[1] += cx > 0 ? v : -v;
+    if (cx && cy) r[2] += cy > 0 ? v : -v;
+    if (cy && cz) r[3] += cy > 0 ? v : -v;
+    if (cx && cz) r[4] += cz > 0 ? v : -v;
+    if (cy && cz) r[5] += cz > 0 ? v : -v;
+    if (cx && cy && cz) r[6] += (cx * cy * cz) > 0 ? v : -v;
+  });
+}
+
+template <typename CT>
+LBM_HD void third_central(const CT (&r)[7], CT ir, CT ux, CT uy, CT uz, CT dxx, CT dyy, CT dzz,
+                          CT dxy, CT dxz, CT dyz, CT (&k)[7]) {
+  const CT third = CT(1.0 / 3.0);
+  k[0] = r[0] * ir - ux * (third + dyy) - CT(2) * uy * dxy - ux * uy * uy;
+  k[1] = r[1] * ir - ux * (third + dzz) - CT(2) * uz * dxz - ux * uz * uz;
+  k[2] = r[2] * ir - uy * (third + dxx) - CT(2) * ux * dxy - uy * ux * ux;
+  k[3] = r[3] * ir - uy * (third + dzz) - CT(2) * uz * dyz - uy * uz * uz;
+  k[4] = r[4] * ir - uz * (third + dxx) - CT(2) * ux * dxz - uz * ux * ux;
+  k[5] = r[5] * ir - uz * (third + dyy) - CT(2) * uy * dyz - uz * uy * uy;
+  k[6] = r[6] * ir - ux * dyz - uy * dxz - uz * dxy - ux * uy * uz;
+}
+
 // post-collision cumulants of orders 3..6 (of f / rho, zero mean)
 template <typename CT>
 struct HighCumulants {
@@ -501,21 +538,8 @@ template <class LS, typename CT>
 LBM_HD void collide_cumulant27_param(CT* g, CT* ph, const Phys<CT>& p) {
   CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
   flow_moments<Q27>(g, drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz);
-  // raw third-order sums r_abc = sum_q cx^a cy^b cz^c g_q
-  CT r120 = CT(0), r102 = CT(0), r210 = CT(0), r012 = CT(0), r201 = CT(0), r021 = CT(0),
-     r111 = CT(0);
-  static_for<0, 27>([&](auto qc) {
-    constexpr int q = decltype(qc)::value;
-    constexpr int cx = Q27::cx[q], cy = Q27::cy[q], cz = Q27::cz[q];
-    const CT v = g[q];
-    if (cx && cy) r120 += cx > 0 ? v : -v;
-    if (cx && cz) r102 += cx > 0 ? v : -v;
-    if (cx && cy) r210 += cy > 0 ? v : -v;
-    if (cy && cz) r012 += cy > 0 ? v : -v;
-    if (cx && cz) r201 += cz > 0 ? v : -v;
-    if (cy && cz) r021 += cz > 0 ? v : -v;
-    if (cx && cy && cz) r111 += (cx * cy * cz) > 0 ? v : -v;
-  });
+  CT r3[7];
+  third_raw_sums<CT>(g, r3);
   const CT chi = scalar_sum<LS>(ph);
   const CT rho = CT(1) + drho;
   const CT irho = CT(1) / rho;
@@ -529,15 +553,11 @@ LBM_HD void collide_cumulant27_param(CT* g, CT* ph, const Phys<CT>& p) {
   CT dxy = pxy * irho - ux * uy;
   CT dxz = pxz * irho - ux * uz;
   CT dyz = pyz * irho - uy * uz;
-  // third-order central moments (= cumulants): E[(X-a)(Y-b)^2] =
-  // E[X Y^2] - a var(Y) - 2 b cov(X,Y) - a b^2, var(Y) = 1/3 + D_yy
-  const CT k120 = r120 * irho - ux * (third + dyy) - CT(2) * uy * dxy - ux * uy * uy;
-  const CT k102 = r102 * irho - ux * (third + dzz) - CT(2) * uz * dxz - ux * uz * uz;
-  const CT k210 = r210 * irho - uy * (third + dxx) - CT(2) * ux * dxy - uy * ux * ux;
-  const CT k012 = r012 * irho - uy * (third + dzz) - CT(2) * uz * dyz - uy * uz * uz;
-  const CT k201 = r201 * irho - uz * (third + dxx) - CT(2) * ux * dxz - uz * ux * ux;
-  const CT k021 = r021 * irho - uz * (third + dyy) - CT(2) * uy * dyz - uz * uy * uy;
-  const CT k111 = r111 * irho - ux * dyz - uy * dxz - uz * dxy - ux * uy * uz;
+  // third-order central moments (= cumulants)
+  CT k3[7];
+  third_central<CT>(r3, irho, ux, uy, uz, dxx, dyy, dzz, dxy, dxz, dyz, k3);
+  const CT k120 = k3[0], k102 = k3[1], k210 = k3[2], k012 = k3[3], k201 = k3[4], k021 = k3[5],
+           k111 = k3[6];
   // velocity gradients from the pre-collision second-order cumulants
   const CT w1 = CT(1) / p.tau0;
   const CT div = CT(-1.5) * p.omega2 * (dxx + dyy + dzz);

@@ -151,6 +151,40 @@ def test_full_size_adjoint_equals_derivative_of_the_forward_map():
         assert abs(a - b) <= 1e-3 * abs(b), name
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("kw", [
+    dict(nx=70, ny=3, nz=6, model=0, cs_smag=0.1),            # ragged x tail, one node per thread
+    dict(nx=1024, ny=64, nz=128, model=0, cs_smag=0.1),       # two nodes per thread
+    dict(nx=1024, ny=64, nz=128, model=1, cs_smag=0.1),       # BGK, two nodes per thread
+    dict(nx=200, ny=5, nz=9, model=2, cs_smag=0.0),           # FCM scalar
+    dict(nx=1024, ny=64, nz=128, model=0, cs_smag=0.0, parametrized=True, limiter=1e-2),
+], ids=["ragged", "npt2", "bgk_npt2", "fcm", "parametrised_npt2"])
+def test_fused_wall_friction_sums_match_the_diagnostics(kw):
+    """The adjoint's forward pass sums F_w inside the step kernel; with
+    w_front = 0, J is the mean of F_w(m), m = 1..n. It must equal the mean of
+    the diagnostics kernel's F_w over a plain run of the same steps (FP64:
+    only the order of the sums and the compiler's contractions differ)."""
+    n = 30
+    cfg = pkg.Config(storage=pkg.F64, re_b=1000.0, g_prime=1e-4, sc_t=1.0, **kw)
+    lat = pkg.Lattice(cfg)
+    lat.init_lock_exchange(0.125, 1e-3, 0)
+    J = lat.adjoint_run(n, 7, 0.0, 1.0)[0]
+    lat.close()
+    lat = pkg.Lattice(cfg)
+    lat.init_lock_exchange(0.125, 1e-3, 0)
+    fws, umax = [], 0.0
+    for _ in range(n):
+        lat.step(1)
+        d = lat.diagnostics()
+        fws.append(d["fw"])
+        umax = max(umax, d["umax"])
+    nu0 = lat.params["nu0"]
+    lat.close()
+    scale = nu0 * 3.0 * umax * cfg.nx * cfg.ny
+    print(f"{kw}: J {J:.15e} mean F_w {np.mean(fws):.15e} scale {scale:.3e}", flush=True)
+    assert abs(J - np.mean(fws)) <= 1e-11 * scale
+
+
 def test_autograd_function_returns_the_library_gradient():
     kw = TINY[0]
     chi0 = olbm.chi0_lock_exchange(OConfig(**kw), 0.125, 1e-3, 4).to("cuda").requires_grad_(True)

@@ -191,7 +191,6 @@ struct AdjLayout {
 
 AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, int64_t k) {
   AdjLayout L;
-  const int64_t n = (int64_t)c->nx * c->ny * c->nz;
   const int qt = p->q_flow + p->q_scalar;
   // population states (checkpoints, trajectory) and the two adjoint buffers
   // share the population buffers' x-blocked layout and slot size

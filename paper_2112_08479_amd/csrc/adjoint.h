@@ -16,9 +16,9 @@
 
 namespace lbm {
 
-// adjoint of inv1d
+// adjoint of inv1d (linear in o2, so o2's own value is not needed)
 template <typename CT>
-LBM_HD void inv1d_vjp(CT o0, CT o1, CT o2, CT u, CT K, CT btm, CT bt0, CT btp, CT& bo0, CT& bo1,
+LBM_HD void inv1d_vjp(CT o0, CT o1, CT /*o2*/, CT u, CT K, CT btm, CT bt0, CT btp, CT& bo0, CT& bo1,
                       CT& bo2, CT& bu) {
   const CT A = K + o0, uu = u * u;
   bo0 = bt0 * (CT(1) - uu) + CT(0.5) * (btp * (uu + u) + btm * (uu - u));

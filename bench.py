@@ -231,9 +231,18 @@ def cpu_baseline(budget_s=15.0):
         if time.time() - t0 > budget_s or k >= 50:
             break
     dt = time.time() - t0
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": n * k / dt / 1e6, "unit": "MNUPS", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle, {k} steps of a 1024x64x8 slab (z-layers of the "
-                      f"1024x64x128 workload, same parameters), {dt:.1f} s"}
+                      f"1024x64x128 workload, same parameters), {dt:.1f} s on {cores} threads of {cpu}"}
 
 
 def main():

@@ -60,7 +60,8 @@ def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0, par
     and no LES, Re_b = 30000). MNUPS counts the n_steps node updates of the
     differentiated run; the algorithmic bytes per node update are a forward
     (2 Q 4 B), its recompute (2 Q 4 B) and the reverse step (3 Q 4 B), Q the
-    populations per node."""
+    populations per node. The workspace is allocated before the timed
+    region; the run is timed with HIP events on the library's stream."""
     import torch
 
     import paper_2112_08479_amd as pkg
@@ -71,11 +72,17 @@ def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0, par
         cfg = pkg.Config(nx, ny, nz, model=model, storage=pkg.F32, re_b=1000.0, cs_smag=0.1, sc_t=1.0)
     lat = pkg.Lattice(cfg)
     lat.init_lock_exchange(0.125, 1e-3, 0)
+    # workspace and gradient buffer allocated before the timed region
+    ws = torch.empty(lat.adjoint_workspace_bytes(n_steps, k_ckpt), dtype=torch.uint8, device="cuda")
+    gchi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-    t0 = time.time()
-    J, dcs, dsct, g = lat.adjoint_run(n_steps, k_ckpt)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    J, dcs, dsct, g = lat.adjoint_run(n_steps, k_ckpt, ws=ws, gchi=gchi)
+    e1.record(lat.stream)
     torch.cuda.synchronize()
-    dt = time.time() - t0
+    dt = e0.elapsed_time(e1) * 1e-3
+    del ws, gchi
     n = cfg.n
     q = lat.params["q_flow"] + lat.params["q_scalar"]
     lat.close()
@@ -90,6 +97,17 @@ def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0, par
             "J": J, "dJ_dcs": dcs, "dJ_dsct": dsct, "hbm_frac": mnups * 1e6 * bpn / 1e9 / HBM_PEAK_GBS,
             "note": ("state fits the 256 MB last-level cache and the run is launch bound: not an HBM "
                      "roofline case" if n * q * 4 < (256 << 20) else "HBM resident")}
+
+
+# adjoint runs: the 256 x 16 x 32 workload (2000 steps, checkpoints every 100)
+# and 100 steps of the benchmark grid (checkpoints every 25)
+ADJOINT_RUNS = {
+    "c3_cumulant27_q7": dict(),
+    "cumulant27_q7_1024x64x128": dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25),
+    "cumulant27_fcm27_1024x64x128": dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25, model=2),
+    "cumulant27param_fcm27_1024x64x128": dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25, model=2,
+                                              param=True),
+}
 
 
 def precision_report(steps=2000):
@@ -255,6 +273,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", action="store_true",
                     help="only the FP16/BF16 vs FP32 storage comparison on 2048x128x256")
+    ap.add_argument("--adjoint", choices=sorted(ADJOINT_RUNS) + ["all"],
+                    help="only the differentiation form: one adjoint run per JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -263,6 +283,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.precision:
         print(json.dumps(precision_report()), flush=True)
+        return
+    if args.adjoint:
+        # the plain copy kernel runs first: it calibrates the HBM byte counters
+        # of a profile taken of this command
+        copy = stream_copy()
+        print(json.dumps({"progress": "stream_copy", **copy}), file=sys.stderr, flush=True)
+        for name in (sorted(ADJOINT_RUNS) if args.adjoint == "all" else [args.adjoint]):
+            print(json.dumps(measure_adjoint(**ADJOINT_RUNS[name])), flush=True)
         return
     copy = stream_copy()
     print(json.dumps({"progress": "stream_copy", **copy}), file=sys.stderr, flush=True)
@@ -276,10 +304,8 @@ def main():
             r = measure(v, max(50, args.steps // 4), min(args.warmup, 50))
             print(json.dumps({"progress": "variant", **r}), file=sys.stderr, flush=True)
             variants.append(r)
-        for kw in (dict(), dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25),
-                   dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25, model=2),
-                   dict(nx=1024, ny=64, nz=128, n_steps=100, k_ckpt=25, model=2, param=True)):
-            r = measure_adjoint(**kw)
+        for name in sorted(ADJOINT_RUNS):
+            r = measure_adjoint(**ADJOINT_RUNS[name])
             print(json.dumps({"progress": "adjoint", **r}), file=sys.stderr, flush=True)
             variants.append(r)
     cpu = None if args.no_cpu_baseline else cpu_baseline()

@@ -26,7 +26,8 @@
  *     named *_dev are device pointers, host_* are host pointers.
  *   - Work is queued on the caller's HIP stream in order. Only
  *     lbm_diagnostics, lbm_get_populations, lbm_set_populations,
- *     lbm_checkpoint_load and lbm_adjoint_run synchronise that stream.
+ *     lbm_checkpoint_save, lbm_checkpoint_load and lbm_adjoint_run
+ *     synchronise that stream.
  *   - Node (i, j, k) has linear index i + nx (j + ny k); x = i is the
  *     streamwise direction, y = j the span, z = k the vertical (gravity
  *     along -z, Eq. 10). Fields passed in or out (chi0, moments, gradients,
@@ -166,7 +167,9 @@ int lbm_derive_params(const lbm_config* cfg, lbm_params* out);
  * buffers (read / write) plus reduction scratch. 0 if cfg is invalid. */
 size_t lbm_workspace_bytes(const lbm_config* cfg);
 
-/* Host only. Bytes of one checkpoint slot: one population buffer + step. */
+/* Host only. Bytes of one checkpoint slot: one population buffer and a
+ * header (grid, model, storage, step counter, gate index, diagnostics at
+ * initialisation). */
 size_t lbm_state_bytes(const lbm_config* cfg);
 
 /* Validates cfg (LBM_EINVAL, before any device work), checks for a GPU
@@ -221,11 +224,17 @@ int lbm_diagnostics(lbm_handle* h, lbm_diag* out);
 /* Step counter of the handle. */
 int lbm_get_step(const lbm_handle* h, int64_t* step);
 
-/* Copies the population buffer and the step counter into a caller device
- * slot of lbm_state_bytes(cfg) bytes (asynchronous). */
+/* Copies the population buffer and the header (grid, model, storage, step
+ * counter, gate index x0, the diagnostics recorded at initialisation) into a
+ * caller device slot of lbm_state_bytes(cfg) bytes; synchronises. */
 int lbm_checkpoint_save(lbm_handle* h, void* dev_slot);
-/* Restores a slot written by lbm_checkpoint_save for the same configuration
- * (synchronises to read the step counter back). */
+/* Restores a slot written by lbm_checkpoint_save into this handle, which may
+ * be a fresh one (never initialised): the populations, the step counter, the
+ * gate index and the initial diagnostics (mass0, chi_mass0), so that later
+ * diagnostics match those of the saved run. LBM_EINVAL, with the handle left
+ * unchanged, if the slot's header is not a checkpoint's or its grid, model or
+ * storage differ from the handle's (the physics parameters may differ: a run
+ * may be continued with another C_s, say). Synchronises. */
 int lbm_checkpoint_load(lbm_handle* h, const void* dev_slot);
 
 /* Test hooks. Pre-collision populations at the current step as full values

@@ -276,19 +276,29 @@ class Lattice:
     def checkpoint_load(self, slot):
         check(self.L.lbm_checkpoint_load(self.h, _ptr(slot)))
 
-    def adjoint_run(self, n_steps, k_ckpt=100, w_front=1.0, w_fw=1.0):
-        """Runs the forward n_steps from the current (initial) state and the
-        hand-written adjoint. Returns (J, dJ/dC_s, dJ/dSc_T, dJ/dchi0 tensor)."""
-        torch = self.torch
+    def adjoint_workspace_bytes(self, n_steps, k_ckpt=100):
         nb = int(self.L.lbm_adjoint_workspace_bytes(ctypes.byref(self.cfg.c()), int(n_steps), int(k_ckpt)))
         if nb == 0:
             check(LBM_EINVAL)
-        ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
-        gchi = torch.empty((self.cfg.nz, self.cfg.ny, self.cfg.nx), dtype=torch.float64, device=self.device)
+        return nb
+
+    def adjoint_run(self, n_steps, k_ckpt=100, w_front=1.0, w_fw=1.0, ws=None, gchi=None):
+        """Runs the forward n_steps from the current (initial) state and the
+        hand-written adjoint. Returns (J, dJ/dC_s, dJ/dSc_T, dJ/dchi0 tensor).
+        ws (uint8, adjoint_workspace_bytes) and gchi (float64, nz*ny*nx) may
+        be given as preallocated device tensors; else they are allocated."""
+        torch = self.torch
+        nb = self.adjoint_workspace_bytes(n_steps, k_ckpt)
+        if ws is None:
+            ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        if gchi is None:
+            gchi = torch.empty((self.cfg.nz, self.cfg.ny, self.cfg.nx), dtype=torch.float64, device=self.device)
+        if ws.numel() * ws.element_size() < nb or gchi.dtype != torch.float64 or gchi.numel() != self.cfg.n:
+            raise ValueError("adjoint workspace or gradient buffer of the wrong size or type")
         J, dcs, dsct = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         check(self.L.lbm_adjoint_run(self.h, int(n_steps), int(k_ckpt), float(w_front), float(w_fw),
-                                     _ptr(ws), nb, ctypes.byref(J), ctypes.byref(dcs),
-                                     ctypes.byref(dsct), _ptr(gchi)))
+                                     _ptr(ws), ws.numel() * ws.element_size(), ctypes.byref(J),
+                                     ctypes.byref(dcs), ctypes.byref(dsct), _ptr(gchi)))
         return J.value, dcs.value, dsct.value, gchi
 
 

@@ -3,6 +3,7 @@
 // records a message retrievable with lbm_last_error().
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stddef.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -35,6 +36,9 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// a checkpoint slot: this many header bytes, then one population buffer
+constexpr size_t kCkptHeaderBytes = 256;
 
 size_t storage_bytes(int storage) {
   switch (storage) {
@@ -338,7 +342,7 @@ size_t lbm_workspace_bytes(const lbm_config* cfg) {
 size_t lbm_state_bytes(const lbm_config* cfg) {
   lbm_params p;
   if (validate(cfg, &p) != LBM_OK) return 0;
-  return layout_of(cfg, &p).buf + 256;
+  return kCkptHeaderBytes + layout_of(cfg, &p).buf;
 }
 
 int lbm_create(const lbm_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
@@ -500,19 +504,42 @@ int lbm_diagnostics(lbm_handle* h, lbm_diag* out) {
   return LBM_OK;
 }
 
+// Header of a checkpoint slot, in its first 256 bytes (the population buffer
+// follows): the configuration it belongs to, the step counter, the gate index
+// and the diagnostics at initialisation (so that a fresh handle restored from
+// the slot reports mass drift and front position against the saved run's
+// start). The header comes first so that reading it stays inside any slot,
+// whichever configuration wrote it; the populations are copied only once it
+// matches the handle's.
+struct CkptHeader {
+  uint64_t magic;
+  int32_t nx, ny, nz, model, storage, x0;
+  int64_t step;
+  double d0[8];
+};
+constexpr uint64_t kCkptMagic = 0x31544B43504D424Cull;  // "LBMPCKT1"
+static_assert(sizeof(CkptHeader) <= kCkptHeaderBytes, "checkpoint header must fit its 256 bytes");
+
 int lbm_checkpoint_save(lbm_handle* h, void* dev_slot) {
   int rc = require_ready(h);
   if (rc) return rc;
   if (!dev_slot) return fail(LBM_EINVAL, "slot is NULL");
   rc = set_device(h);
   if (rc) return rc;
-  const size_t sb = h->state_bytes;
-  HIPCHECK(lbm::launch_copy_state(h, h->buf[h->cur], dev_slot));
-  // the step counter follows the populations (256-byte aligned)
-  static thread_local int64_t stepbuf;
-  stepbuf = h->step;
-  HIPCHECK(hipMemcpyAsync((char*)dev_slot + align256(sb), &stepbuf, sizeof(int64_t),
-                          hipMemcpyHostToDevice, h->stream));
+  char* hdr = (char*)dev_slot;
+  HIPCHECK(lbm::launch_copy_state(h, h->buf[h->cur], hdr + kCkptHeaderBytes));
+  static thread_local CkptHeader hh;
+  hh.magic = kCkptMagic;
+  hh.nx = h->cfg.nx;
+  hh.ny = h->cfg.ny;
+  hh.nz = h->cfg.nz;
+  hh.model = h->cfg.model;
+  hh.storage = h->cfg.storage;
+  hh.x0 = h->x0;
+  hh.step = h->step;
+  HIPCHECK(hipMemcpyAsync(hdr, &hh, offsetof(CkptHeader, d0), hipMemcpyHostToDevice, h->stream));
+  HIPCHECK(hipMemcpyAsync(hdr + offsetof(CkptHeader, d0), h->d0, sizeof(hh.d0), hipMemcpyDeviceToDevice,
+                          h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
   return LBM_OK;
 }
@@ -522,13 +549,25 @@ int lbm_checkpoint_load(lbm_handle* h, const void* dev_slot) {
   if (!dev_slot) return fail(LBM_EINVAL, "slot is NULL");
   int rc = set_device(h);
   if (rc) return rc;
-  const size_t sb = h->state_bytes;
-  HIPCHECK(lbm::launch_copy_state(h, dev_slot, h->buf[h->cur]));
-  int64_t s = 0;
-  HIPCHECK(hipMemcpyAsync(&s, (const char*)dev_slot + align256(sb), sizeof(int64_t),
-                          hipMemcpyDeviceToHost, h->stream));
+  const char* hdr = (const char*)dev_slot;
+  CkptHeader hh;
+  HIPCHECK(hipMemcpyAsync(&hh, hdr, offsetof(CkptHeader, d0), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
-  h->step = s;
+  if (hh.magic != kCkptMagic)
+    return fail(LBM_EINVAL, "slot does not hold a checkpoint (bad header)");
+  const lbm_config& c = h->cfg;
+  if (hh.nx != c.nx || hh.ny != c.ny || hh.nz != c.nz || hh.model != c.model || hh.storage != c.storage)
+    return fail(LBM_EINVAL, "checkpoint of a %d x %d x %d grid, model %d, storage %d does not match "
+                "the handle's %d x %d x %d, model %d, storage %d", hh.nx, hh.ny, hh.nz, hh.model,
+                hh.storage, c.nx, c.ny, c.nz, c.model, c.storage);
+  if (hh.step < 0 || hh.x0 < 0 || hh.x0 >= c.nx)
+    return fail(LBM_EINVAL, "checkpoint header holds step %lld, gate %d", (long long)hh.step, hh.x0);
+  HIPCHECK(lbm::launch_copy_state(h, hdr + kCkptHeaderBytes, h->buf[h->cur]));
+  HIPCHECK(hipMemcpyAsync(h->d0, hdr + offsetof(CkptHeader, d0), sizeof(hh.d0), hipMemcpyDeviceToDevice,
+                          h->stream));
+  HIPCHECK(hipStreamSynchronize(h->stream));
+  h->step = hh.step;
+  h->x0 = hh.x0;
   h->initialised = true;
   return LBM_OK;
 }

@@ -16,6 +16,9 @@ void check(int nx, int ny, int nz, int kBlock) {
   const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
   const int nbx = (nx + bx * NPT - 1) / (bx * NPT);
   std::vector<char> stored(total, 0);
+  // base of the reference pull's pointer arithmetic (never dereferenced)
+  std::vector<float> buf(total + 1);
+  const float* base0 = buf.data();
   for (int row = 0; row < ny * nz; ++row) {
     const int y = row % ny, z = row / ny;
     for (int tb = 0; tb < nbx; ++tb) {
@@ -37,8 +40,8 @@ void check(int nx, int ny, int nz, int kBlock) {
               if (L::cx[q] != 0 && (bidx < 0 || bidx >= total)) { ++fails; printf("fixup OOB\n"); }
               if (t.x[k] < nx) {
                 const int64_t eff = x_wall<L, q>(g, t.x[k], zw) ? bidx : idx;
-                const float* ref = pull_ptr<L, q, QT>((const float*)nullptr, g, base, t.x[k], y, z);
-                if ((int64_t)(ref - (const float*)nullptr) != eff) { ++fails; if (fails < 10) printf("mismatch %d %d %d row %d x %d q %d\n", nx, ny, nz, row, t.x[k], q); }
+                const float* ref = pull_ptr<L, q, QT>(base0, g, base, t.x[k], y, z);
+                if ((int64_t)(ref - base0) != eff) { ++fails; if (fails < 10) printf("mismatch %d %d %d row %d x %d q %d\n", nx, ny, nz, row, t.x[k], q); }
               }
             }
           });

@@ -208,6 +208,39 @@ def test_checkpoint_roundtrip_is_bitwise():
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def test_checkpoint_restores_into_a_fresh_handle():
+    """A slot saved by one lattice restores into a new, never initialised
+    lattice: same populations, step counter, gate position and initial
+    diagnostics, so mass drift and the front read as in the saved run; a
+    handle of another grid or storage refuses the slot."""
+    kw = dict(C0, cs_smag=0.1)
+    cfg, P = both(pkg.F32, **kw)
+    a = pkg.Lattice(cfg)
+    a.init_lock_exchange(0.25, 1e-3, 3)          # gate at nx/4, not the default nx/8
+    a.step(11)
+    slot = a.checkpoint_save()
+    da = a.diagnostics()
+    a.step(5)
+    pa = a.get_populations()
+    b = pkg.Lattice(cfg)
+    b.checkpoint_load(slot)
+    assert b.step_count == 11
+    db = b.diagnostics()
+    for key in ("mass", "mass0", "chi_mass", "chi_mass0", "x_front", "x_f", "fw", "umax"):
+        assert db[key] == da[key], (key, db[key], da[key])
+    b.step(5)
+    pb = b.get_populations()
+    assert np.array_equal(pa[0], pb[0]) and np.array_equal(pa[1], pb[1])
+    for other in (dict(kw, nx=kw["nx"] + 64), dict(kw, model=1)):
+        c = pkg.Lattice(both(pkg.F32, **other)[0])
+        with pytest.raises(pkg.LBMError) as e:
+            c.checkpoint_load(slot)
+        assert e.value.code == pkg.LBM_EINVAL
+    c = pkg.Lattice(both(pkg.F64, **kw)[0])
+    with pytest.raises(pkg.LBMError):
+        c.checkpoint_load(slot)
+
+
 @pytest.mark.parametrize("model", [0, 1, 2])
 @pytest.mark.parametrize("storage", [pkg.F64, pkg.F32])
 def test_rest_state_stays_exactly_at_rest(model, storage):

@@ -58,9 +58,10 @@ def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0, par
     recompute, hand-written adjoint) of the lock exchange, FP32, Re_b = 1000,
     C_s = 0.1, Sc_T = 1 (param: the parametrised cumulant with limiter 1e-2
     and no LES, Re_b = 30000). MNUPS counts the n_steps node updates of the
-    differentiated run; the algorithmic bytes per node update are a forward
-    (2 Q 4 B), its recompute (2 Q 4 B) and the reverse step (3 Q 4 B), Q the
-    populations per node. The workspace is allocated before the timed
+    differentiated run; the algorithmic bytes are those of the passes made: a
+    forward step (2 Q 4 B per node) per step, one per recomputed step, a
+    reverse step (3 Q 4 B) per step and one initial copy, Q the populations
+    per node. The workspace is allocated before the timed
     region; the run is timed with HIP events on the library's stream."""
     import torch
 
@@ -86,13 +87,18 @@ def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0, par
     n = cfg.n
     q = lat.params["q_flow"] + lat.params["q_scalar"]
     lat.close()
-    bpn = 2 * q * 4 + 2 * q * 4 + 3 * q * 4
+    # the passes actually made: n forward steps, the recomputed steps of every
+    # segment but the last (whose states the forward pass kept), n reverse
+    # steps, and the copy of the initial state into the first checkpoint
+    nseg = -(-n_steps // k_ckpt)
+    recomputed = (nseg - 1) * (k_ckpt - 1)
+    bpn = (n_steps * 2 * q * 4 + recomputed * 2 * q * 4 + n_steps * 3 * q * 4 + 2 * q * 4) / n_steps
     mnups = n * n_steps / dt / 1e6
     name = ["cumulant27_q7", "bgk19_smag_q6", "cumulant27_fcm27"][model]
     if param:
         name = name.replace("cumulant27", "cumulant27param")
     return {"workload": f"adjoint_{name}_{nx}x{ny}x{nz}_fp32_{n_steps}steps_k{k_ckpt}",
-            "nodes": n, "steps": n_steps, "seconds": dt, "MNUPS": mnups,
+            "nodes": n, "steps": n_steps, "recomputed_steps": recomputed, "seconds": dt, "MNUPS": mnups,
             "bytes_per_node_update": bpn, "GB_per_s": mnups * 1e6 * bpn / 1e9,
             "J": J, "dJ_dcs": dcs, "dJ_dsct": dsct, "hbm_frac": mnups * 1e6 * bpn / 1e9 / HBM_PEAK_GBS,
             "note": ("state fits the 256 MB last-level cache and the run is launch bound: not an HBM "

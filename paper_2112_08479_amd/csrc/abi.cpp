@@ -200,7 +200,9 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, 
   // share the population buffers' x-blocked layout and slot size
   L.buf = align256(state_bytes_of(c, qt) + lbm::kBufferGuardBytes);
   L.nseg = (n_steps + k - 1) / k;
-  L.ktraj = k < n_steps ? k : n_steps;
+  // a segment's first state is its checkpoint; the trajectory slots hold
+  // the other k - 1 (fewer when the run is shorter)
+  L.ktraj = (k < n_steps ? k : n_steps) - 1;
   const int bx = block_x(c->nx);
   const int64_t ablocks = (int64_t)((c->nx + bx - 1) / bx) * c->ny * c->nz;
   const int64_t fblocks = (int64_t)lbm::xblocks(c->nx) * c->ny * std::min(c->nz, 2);
@@ -264,27 +266,47 @@ int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_fro
   const int nblk = lbm::adjoint_blocks(h);
   const size_t sbytes = h->state_bytes;
   auto ckpt = [&](int64_t s) { return (void*)(ws + L.ckpt + (size_t)s * L.buf); };
-  auto traj = [&](int64_t i) { return (void*)(ws + L.traj + (size_t)i * L.buf); };
   HIPCHECK(lbm::launch_zero(h, gpart, 2 * (int64_t)nblk));
   HIPCHECK(lbm::launch_zero(h, small, 32));
-  // forward with checkpoints; the wall-layer sums of F_w(m), m = 1..n, go to
-  // one slot set per step (slot m - 1) and are reduced once, in fixed order,
-  // at the end. Step m -> m + 1 gathers state m and writes F_w(m) itself; the
-  // final state's F_w(n) takes the separate wall-layer kernel. Every forward
-  // and recomputed step runs the same kernel (step 0 and the recomputation
-  // write into the spare slot set), so the recomputed states are bitwise the
-  // checkpointed trajectory's whatever the checkpoint interval.
+  // Storage of the forward states. State m of segment s (m0 = s k_ckpt <= m <
+  // e) is checkpoint s when m = m0, else trajectory slot m - m0 (1 .. k - 1).
+  // The forward pass writes every checkpoint state straight into its slot and
+  // the states of the last segment straight into the trajectory, so the
+  // reverse pass recomputes every segment but the last and copies nothing;
+  // the other states go through the handle's two buffers, and the final state
+  // n ends in the handle's current buffer.
+  auto traj_slot = [&](int64_t i) { return (void*)(ws + L.traj + (size_t)(i - 1) * L.buf); };
+  auto state_of = [&](int64_t m) {
+    const int64_t s = m / k_ckpt, m0 = s * k_ckpt;
+    return m == m0 ? ckpt(s) : traj_slot(m - m0);
+  };
+  const int64_t last = L.nseg - 1;
+  // forward; the wall-layer sums of F_w(m), m = 1..n, go to one slot set per
+  // step (slot m - 1) and are reduced once, in fixed order, at the end. Step
+  // m -> m + 1 gathers state m and writes F_w(m) itself; the final state's
+  // F_w(n) takes the separate wall-layer kernel. Every forward and recomputed
+  // step runs the same kernel (step 0 and the recomputation write into the
+  // spare slot set), so the recomputed states are bitwise the forward pass's
+  // whatever the checkpoint interval.
   const int fwb = lbm::fw_blocks(h);
   double* fw_spare = fwpart + 2 * (size_t)fwb * n_steps;
-  for (int64_t s = 0; s < L.nseg; ++s) {
-    HIPCHECK(hipMemcpyAsync(ckpt(s), h->buf[h->cur], sbytes, hipMemcpyDeviceToDevice, h->stream));
-    const int64_t steps = std::min<int64_t>(k_ckpt, n_steps - s * k_ckpt);
-    for (int64_t i = 0; i < steps; ++i) {
-      double* fw = h->step >= 1 ? fwpart + 2 * (size_t)fwb * (h->step - 1) : fw_spare;
-      HIPCHECK(lbm::launch_step(h, h->buf[h->cur], h->buf[h->cur ^ 1], fw));
-      h->cur ^= 1;
-      h->step += 1;
+  HIPCHECK(hipMemcpyAsync(ckpt(0), h->buf[h->cur], sbytes, hipMemcpyDeviceToDevice, h->stream));
+  const void* cur = ckpt(0);
+  for (int64_t m = 0; m < n_steps; ++m) {
+    const int64_t mn = m + 1;
+    void* dst;
+    if (mn == n_steps) {
+      h->cur = (cur == h->buf[0]) ? 1 : 0;
+      dst = h->buf[h->cur];
+    } else if (mn % k_ckpt == 0 || mn / k_ckpt == last) {
+      dst = state_of(mn);
+    } else {
+      dst = (cur == h->buf[0]) ? h->buf[1] : h->buf[0];
     }
+    double* fw = m >= 1 ? fwpart + 2 * (size_t)fwb * (m - 1) : fw_spare;
+    HIPCHECK(lbm::launch_step(h, cur, dst, fw));
+    cur = dst;
+    h->step += 1;
   }
   HIPCHECK(lbm::launch_fw_layers(h, h->buf[h->cur], fwpart + 2 * (size_t)fwb * (n_steps - 1)));
   HIPCHECK(lbm::launch_fw_reduce(h, fwpart, n_steps * fwb, small));
@@ -297,15 +319,16 @@ int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_fro
   void* lam_out = ws + L.lam + L.buf;
   HIPCHECK(lbm::launch_adjoint_seed(h, h->buf[h->cur], lam_next, a0, a1, small + 8));
   // reverse sweep over the segments, recomputing each from its checkpoint
-  for (int64_t s = L.nseg - 1; s >= 0; --s) {
+  // (the last segment's states are still in the trajectory)
+  for (int64_t s = last; s >= 0; --s) {
     const int64_t m0 = s * k_ckpt;
     const int64_t e = std::min<int64_t>(m0 + k_ckpt, n_steps);
-    HIPCHECK(hipMemcpyAsync(traj(0), ckpt(s), sbytes, hipMemcpyDeviceToDevice, h->stream));
-    for (int64_t i = 0; i + 1 < e - m0; ++i)
-      HIPCHECK(lbm::launch_step(h, traj(i), traj(i + 1), fw_spare));
+    if (s != last)
+      for (int64_t m = m0; m + 1 < e; ++m)
+        HIPCHECK(lbm::launch_step(h, state_of(m), state_of(m + 1), fw_spare));
     for (int64_t m = e - 1; m >= m0; --m) {
       const bool seed = m >= 1;
-      HIPCHECK(lbm::launch_adjoint_step(h, traj(m - m0), lam_next, lam_out, seed ? a0 : 0.0,
+      HIPCHECK(lbm::launch_adjoint_step(h, state_of(m), lam_next, lam_out, seed ? a0 : 0.0,
                                         seed ? a1 : 0.0, gpart, m == 0 ? dJ_dchi0_dev : nullptr));
       std::swap(lam_next, lam_out);
     }

@@ -16,6 +16,16 @@
 
 namespace lbm {
 
+// Keeps the instruction scheduler from moving work across this point (device
+// code; no effect on the host). The adjoints of the post-collision values are
+// loaded behind it, where the chain rule first needs them, so that they are
+// not held in registers through the forward recompute.
+LBM_HD void sched_fence() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
 // adjoint of inv1d (linear in o2, so o2's own value is not needed)
 template <typename CT>
 LBM_HD void inv1d_vjp(CT o0, CT o1, CT /*o2*/, CT u, CT K, CT btm, CT bt0, CT btp, CT& bo0, CT& bo1,
@@ -28,45 +38,83 @@ LBM_HD void inv1d_vjp(CT o0, CT o1, CT /*o2*/, CT u, CT K, CT btm, CT bt0, CT bt
         CT(0.5) * btm * (CT(2) * o1 + (CT(2) * u - CT(1)) * A);
 }
 
+// output S of inv1d alone (0: t(-1), 1: t(0), 2: t(+1))
+template <int S, typename CT>
+LBM_HD CT inv1d_one(CT o0, CT o1, CT o2, CT u, CT K) {
+  const CT A = K + o0, uu = u * u;
+  if constexpr (S == 1)
+    return o0 - o2 - CT(2) * u * o1 - uu * A;
+  else if constexpr (S == 2)
+    return CT(0.5) * (o2 + o1 * (CT(1) + CT(2) * u) + (uu + u) * A);
+  else
+    return CT(0.5) * (o2 + o1 * (CT(2) * u - CT(1)) + (uu - u) * A);
+}
+
+// adjoint of output S of inv1d alone: adds bt's contribution to bo0, bo1,
+// bo2 and bu (the three outputs' terms of inv1d_vjp, one at a time)
+template <int S, typename CT>
+LBM_HD void inv1d_one_vjp(CT o0, CT o1, CT u, CT K, CT bt, CT& bo0, CT& bo1, CT& bo2, CT& bu) {
+  const CT A = K + o0, uu = u * u;
+  if constexpr (S == 1) {
+    bo0 += bt * (CT(1) - uu);
+    bo1 += -CT(2) * u * bt;
+    bo2 += -bt;
+    bu += bt * (-CT(2) * o1 - CT(2) * u * A);
+  } else if constexpr (S == 2) {
+    bo0 += CT(0.5) * bt * (uu + u);
+    bo1 += CT(0.5) * bt * (CT(1) + CT(2) * u);
+    bo2 += CT(0.5) * bt;
+    bu += CT(0.5) * bt * (CT(2) * o1 + (CT(2) * u + CT(1)) * A);
+  } else {
+    bo0 += CT(0.5) * bt * (uu - u);
+    bo1 += CT(0.5) * bt * (CT(2) * u - CT(1));
+    bo2 += CT(0.5) * bt;
+    bu += CT(0.5) * bt * (CT(2) * o1 + (CT(2) * u - CT(1)) * A);
+  }
+}
+
 // adjoint of inverse_chimera: gb (population order) -> mb[9a+3b+c] and the
-// adjoints of the three velocity components
+// adjoints of the three velocity components. The transform is taken one
+// x-velocity slab (c_x = -1, 0, +1) at a time: the slab's nine x-pass values
+// and its y pass are recomputed from m, its z and y passes are reversed, and
+// its share of the reversed x pass is added to mb. Only one slab's
+// intermediates are live at once (the x pass is linear in each output).
 template <typename CT>
 LBM_HD void inverse_chimera_vjp(const CT* m, CT ux, CT uy, CT uz, const CT* gbar, CT* mb, CT& bux,
                                 CT& buy, CT& buz) {
-  CT B[27], A[27], Ab[27], Bb[27];
-  static_for<0, 9>([&](auto ic) {  // forward x pass
-    constexpr int i = decltype(ic)::value, b = i / 3, c = i % 3;
-    constexpr double K = k1d(b) * k1d(c);
-    inv1d<CT>(m[b * 3 + c], m[9 + b * 3 + c], m[18 + b * 3 + c], ux, CT(K), B[b * 3 + c],
-              B[9 + b * 3 + c], B[18 + b * 3 + c]);
-  });
-  static_for<0, 9>([&](auto ic) {  // forward y pass
-    constexpr int i = decltype(ic)::value, cxi = i / 3, c = i % 3;
-    constexpr double K = w1d(cxi) * k1d(c);
-    inv1d<CT>(B[cxi * 9 + c], B[cxi * 9 + 3 + c], B[cxi * 9 + 6 + c], uy, CT(K), A[cxi * 9 + c],
-              A[cxi * 9 + 3 + c], A[cxi * 9 + 6 + c]);
-  });
-  static_for<0, 9>([&](auto ic) {  // reverse z pass
-    constexpr int i = decltype(ic)::value, cxi = i / 3, cyi = i % 3;
-    constexpr double K = w1d(cxi) * w1d(cyi);
-    const int o = cxi * 9 + cyi * 3;
-    inv1d_vjp<CT>(A[o], A[o + 1], A[o + 2], uz, CT(K), gbar[idx27(cxi - 1, cyi - 1, -1)],
-                  gbar[idx27(cxi - 1, cyi - 1, 0)], gbar[idx27(cxi - 1, cyi - 1, 1)], Ab[o], Ab[o + 1],
-                  Ab[o + 2], buz);
-  });
-  static_for<0, 9>([&](auto ic) {  // reverse y pass
-    constexpr int i = decltype(ic)::value, cxi = i / 3, c = i % 3;
-    constexpr double K = w1d(cxi) * k1d(c);
-    const int o = cxi * 9 + c;
-    inv1d_vjp<CT>(B[o], B[o + 3], B[o + 6], uy, CT(K), Ab[o], Ab[o + 3], Ab[o + 6], Bb[o], Bb[o + 3],
-                  Bb[o + 6], buy);
-  });
-  static_for<0, 9>([&](auto ic) {  // reverse x pass
-    constexpr int i = decltype(ic)::value, b = i / 3, c = i % 3;
-    constexpr double K = k1d(b) * k1d(c);
-    const int o = b * 3 + c;
-    inv1d_vjp<CT>(m[o], m[9 + o], m[18 + o], ux, CT(K), Bb[o], Bb[9 + o], Bb[18 + o], mb[o],
-                  mb[9 + o], mb[18 + o], bux);
+  static_for<0, 27>([&](auto ic) { mb[decltype(ic)::value] = CT(0); });
+  static_for<0, 3>([&](auto sc) {
+    constexpr int cxi = decltype(sc)::value;
+    CT Bs[9], As[9], Abs[9], Bbs[9];
+    static_for<0, 9>([&](auto ic) {  // forward x pass, this slab's output
+      constexpr int i = decltype(ic)::value, b = i / 3, c = i % 3;
+      constexpr double K = k1d(b) * k1d(c);
+      Bs[i] = inv1d_one<cxi, CT>(m[i], m[9 + i], m[18 + i], ux, CT(K));
+    });
+    static_for<0, 3>([&](auto cc) {  // forward y pass
+      constexpr int c = decltype(cc)::value;
+      constexpr double K = w1d(cxi) * k1d(c);
+      inv1d<CT>(Bs[c], Bs[3 + c], Bs[6 + c], uy, CT(K), As[c], As[3 + c], As[6 + c]);
+    });
+    static_for<0, 3>([&](auto yc) {  // reverse z pass
+      constexpr int cyi = decltype(yc)::value;
+      constexpr double K = w1d(cxi) * w1d(cyi);
+      const int o = cyi * 3;
+      inv1d_vjp<CT>(As[o], As[o + 1], As[o + 2], uz, CT(K), gbar[idx27(cxi - 1, cyi - 1, -1)],
+                    gbar[idx27(cxi - 1, cyi - 1, 0)], gbar[idx27(cxi - 1, cyi - 1, 1)], Abs[o],
+                    Abs[o + 1], Abs[o + 2], buz);
+    });
+    static_for<0, 3>([&](auto cc) {  // reverse y pass
+      constexpr int c = decltype(cc)::value;
+      constexpr double K = w1d(cxi) * k1d(c);
+      inv1d_vjp<CT>(Bs[c], Bs[3 + c], Bs[6 + c], uy, CT(K), Abs[c], Abs[3 + c], Abs[6 + c], Bbs[c],
+                    Bbs[3 + c], Bbs[6 + c], buy);
+    });
+    static_for<0, 9>([&](auto ic) {  // this slab's share of the reverse x pass
+      constexpr int i = decltype(ic)::value, b = i / 3, c = i % 3;
+      constexpr double K = k1d(b) * k1d(c);
+      inv1d_one_vjp<cxi, CT>(m[i], m[9 + i], ux, CT(K), Bbs[i], mb[i], mb[9 + i], mb[18 + i], bux);
+    });
   });
 }
 
@@ -233,8 +281,8 @@ LBM_HD void flow_moments_vjp(CT bdrho, CT bjx, CT bjy, CT bjz, CT bpxx, CT bpyy,
 
 // ---- cumulant D3Q27 + scalar lattice LS (D3Q7 BGK or D3Q27 FCM),
 // omega3..omega6 = 1
-template <class LS, bool LES, typename CT>
-LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, const CT* mg, const CT* mp,
+template <class LS, bool LES, typename CT, class LoadMG, class LoadMP>
+LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, LoadMG&& load_mg, LoadMP&& load_mp,
                            const Phys<CT>& p, CT* gb, CT* pb, CT& b_cles, CT& b_isct) {
   // ---- forward recompute
   CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
@@ -259,6 +307,9 @@ LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, const CT* mg, const CT* mp
     tau = CT(0.5) * (p.tau0 + R);
   }
   const CT a1 = CT(1) - CT(1) / tau;
+  // d tau / d s = c_les / (4 R) (zero subgradient of sqrt(Q) at Q = 0), over s:
+  // formed here, unconditionally, so that the reverse sweep has no branch
+  const CT cbs = (LES && s > CT(0)) ? p.c_les / (CT(4) * R * s) : CT(0);
   CT exx = dxx, eyy = dyy, ezz = dzz, exy = dxy, exz = dxz, eyz = dyz;
   relax_second(a1, p.omega2, exx, eyy, ezz, exy, exz, eyz);
   const CT T3 = (dxx + dyy + dzz) * third;
@@ -295,10 +346,14 @@ LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, const CT* mg, const CT* mp
   // ---- reverse
   CT bchi = CT(0), bux = CT(0), buy = CT(0), buz = CT(0), btau = CT(0);
   CT buzs = CT(0);
+  CT mp[LS::Q], mg[27];
+  sched_fence();
+  load_mp(mp);
   scalar_collision_vjp<LS, LES, CT>(ph, chi, ux, uy, uzs, tau, p, mp, pb, bchi, bux, buy, buzs, btau,
                                     b_isct);
   CT mb[27];
   CT bvz = CT(0);
+  load_mg(mg);
   inverse_chimera_vjp<CT>(m, ux, uy, vz, mg, mb, bux, buy, bvz);
   CT brho = CT(0), bdrho = CT(0);
   CT bexx = CT(0), beyy = CT(0), bezz = CT(0), bexy = CT(0), bexz = CT(0), beyz = CT(0);
@@ -352,15 +407,13 @@ LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, const CT* mg, const CT* mp
   btau += ba1 / (tau * tau);
   if constexpr (LES) {
     b_cles += btau * s / (CT(4) * R);
-    if (s > CT(0)) {
-      const CT bs = btau * p.c_les / (CT(4) * R) / s;
-      bdxx += bs * dxx;
-      bdyy += bs * dyy;
-      bdzz += bs * dzz;
-      bdxy += bs * CT(2) * dxy;
-      bdxz += bs * CT(2) * dxz;
-      bdyz += bs * CT(2) * dyz;
-    }
+    const CT bs = btau * cbs;
+    bdxx += bs * dxx;
+    bdyy += bs * dyy;
+    bdzz += bs * dzz;
+    bdxy += bs * CT(2) * dxy;
+    bdxz += bs * CT(2) * dxz;
+    bdyz += bs * CT(2) * dyz;
   }
   // D from raw moments
   CT bpxx = bdxx * ir, bpyy = bdyy * ir, bpzz = bdzz * ir;
@@ -389,8 +442,8 @@ LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, const CT* mg, const CT* mp
 // derivative of collide_cumulant27_param. The limited third-order map
 // X -> X (1 - w)(1 - |X| / (|X| + lambda)) has the derivative
 // (1 - w)(1 - q)^2, q = |X| / (|X| + lambda), which is smooth at X = 0.
-template <class LS, typename CT>
-LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, const CT* mg, const CT* mp,
+template <class LS, typename CT, class LoadMG, class LoadMP>
+LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, LoadMG&& load_mg, LoadMP&& load_mp,
                                  const Phys<CT>& p, CT* gb, CT* pb, CT& b_isct) {
   // ---- forward recompute (as collide_cumulant27_param)
   CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
@@ -483,10 +536,14 @@ LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, const CT* mg, const 
 
   // ---- reverse
   CT bchi = CT(0), bux = CT(0), buy = CT(0), buz = CT(0), btau = CT(0), buzs = CT(0);
+  CT mp[LS::Q], mg[27];
+  sched_fence();
+  load_mp(mp);
   scalar_collision_vjp<LS, false, CT>(ph, chi, ux, uy, uzs, p.tau0, p, mp, pb, bchi, bux, buy, buzs,
                                       btau, b_isct);
   CT mb[27];
   CT bvz = CT(0);
+  load_mg(mg);
   inverse_chimera_vjp<CT>(m, ux, uy, vz, mg, mb, bux, buy, bvz);
   CT brho = CT(0), bdrho = mb[0];
   CT r[27];
@@ -636,8 +693,8 @@ LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, const CT* mg, const 
 }
 
 // ---- BGK D3Q19 + Guo + Smagorinsky, D3Q6 scalar
-template <bool LES, typename CT>
-LBM_HD void vjp_bgk_q19_q6(const CT* g, const CT* ph, const CT* mg, const CT* mp, const Phys<CT>& p,
+template <bool LES, typename CT, class LoadMG, class LoadMP>
+LBM_HD void vjp_bgk_q19_q6(const CT* g, const CT* ph, LoadMG&& load_mg, LoadMP&& load_mp, const Phys<CT>& p,
                            CT* gb, CT* pb, CT& b_cles, CT& b_isct) {
   CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
   flow_moments<Q19>(g, drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz);
@@ -658,11 +715,18 @@ LBM_HD void vjp_bgk_q19_q6(const CT* g, const CT* ph, const CT* mg, const CT* mp
     tau = CT(0.5) * (p.tau0 + R);
   }
   const CT w = CT(1) / tau;
+  // 1 / sqrt(Q) with the zero subgradient at Q = 0, formed here so that the
+  // reverse sweep has no branch
+  const CT isq = (LES && sq > CT(0)) ? CT(1) / sq : CT(0);
   const CT usq = ux * ux + uy * uy + uz * uz;
   const CT sfac = CT(1) - CT(0.5) * w;
 
   CT bchi = CT(0), bux = CT(0), buy = CT(0), buz = CT(0), btau = CT(0);
+  CT mp[6], mg[19];
+  sched_fence();
+  load_mp(mp);
   scalar_vjp<Q6, LES, CT>(ph, chi, ux, uy, uz, tau, p, mp, pb, bchi, bux, buy, buz, btau, b_isct);
+  load_mg(mg);
   CT bw = CT(0), bsfac = CT(0), busq = CT(0), bdrho = CT(0), brho = CT(0), bFz = CT(0);
   static_for<0, 19>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
@@ -701,23 +765,21 @@ LBM_HD void vjp_bgk_q19_q6(const CT* g, const CT* ph, const CT* mg, const CT* mp
     b_cles += btau * h / (CT(4) * R);
     const CT bh = btau * p.c_les / (CT(4) * R);
     bir += bh * sq;
-    if (sq > CT(0)) {
-      const CT bsq = bh * ir / sq;
-      const CT bnxx = bsq * nxx, bnyy = bsq * nyy, bnzz = bsq * nzz;
-      const CT bnxy = bsq * CT(2) * nxy, bnxz = bsq * CT(2) * nxz, bnyz = bsq * CT(2) * nyz;
-      bpxx += bnxx;
-      bpyy += bnyy;
-      bpzz += bnzz;
-      bpxy += bnxy;
-      bpxz += bnxz;
-      bpyz += bnyz;
-      bdrho -= (bnxx + bnyy + bnzz) * CT(1.0 / 3.0);
-      brho -= bnxx * ux * ux + bnyy * uy * uy + bnzz * uz * uz + bnxy * ux * uy + bnxz * ux * uz +
-              bnyz * uy * uz;
-      bux -= rho * (CT(2) * ux * bnxx + uy * bnxy + uz * bnxz);
-      buy -= rho * (CT(2) * uy * bnyy + ux * bnxy + uz * bnyz);
-      buz -= rho * (CT(2) * uz * bnzz + ux * bnxz + uy * bnyz);
-    }
+    const CT bsq = bh * ir * isq;
+    const CT bnxx = bsq * nxx, bnyy = bsq * nyy, bnzz = bsq * nzz;
+    const CT bnxy = bsq * CT(2) * nxy, bnxz = bsq * CT(2) * nxz, bnyz = bsq * CT(2) * nyz;
+    bpxx += bnxx;
+    bpyy += bnyy;
+    bpzz += bnzz;
+    bpxy += bnxy;
+    bpxz += bnxz;
+    bpyz += bnyz;
+    bdrho -= (bnxx + bnyy + bnzz) * CT(1.0 / 3.0);
+    brho -= bnxx * ux * ux + bnyy * uy * uy + bnzz * uz * uz + bnxy * ux * uy + bnxz * ux * uz +
+            bnyz * uy * uz;
+    bux -= rho * (CT(2) * ux * bnxx + uy * bnxy + uz * bnxz);
+    buy -= rho * (CT(2) * uy * bnyy + ux * bnxy + uz * bnyz);
+    buz -= rho * (CT(2) * uz * bnzz + ux * bnxz + uy * bnyz);
   }
   CT bjx = bux * ir, bjy = buy * ir, bjz = buz * ir;
   bFz += buz * ir * CT(0.5);

@@ -81,25 +81,26 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(const ST* __restrict__ 
   if (x < g.nx) {
     const int y = row % g.ny, z = row / g.ny;
     const int64_t node = (int64_t)row * g.nx + x;
-    CT fg[LF::Q], ph[LS::Q], mg[LF::Q], mp[LS::Q], gb[LF::Q], pb[LS::Q];
+    CT fg[LF::Q], ph[LS::Q], gb[LF::Q], pb[LS::Q];
     gather<LF, LS, ST, CT>(state, g, x, y, z, fg, ph);
-    static_for<0, LF::Q>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      mg[q] = lam_next[rpull_offset<LF, q, LF::Q + LS::Q>(g, 0, x, y, z)];
-    });
-    static_for<0, LS::Q>([&](auto qc) {
-      constexpr int q = decltype(qc)::value;
-      mp[q] = lam_next[rpull_offset<LS, q, LF::Q + LS::Q>(g, LF::Q, x, y, z)];
-    });
-    CT bc = CT(0), bi = CT(0);
-    if constexpr ((MODEL == 0 || MODEL == 2) && PARAM)
-      vjp_cumulant27_param<LS, CT>(fg, ph, mg, mp, p, gb, pb, bi);
-    else if constexpr (MODEL == 0 || MODEL == 2)
-      vjp_cumulant27<LS, LES, CT>(fg, ph, mg, mp, p, gb, pb, bc, bi);
-    else
-      vjp_bgk_q19_q6<LES, CT>(fg, ph, mg, mp, p, gb, pb, bc, bi);
-    // seed of the wall friction term at this step: d u_x / d g_q = (c_qx - u_x) / rho
+    // reverse pulls of lambda(m + 1), made where the collision's adjoint needs them
+    auto load_mg = [&](CT* mg) {
+      static_for<0, LF::Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        mg[q] = lam_next[rpull_offset<LF, q, LF::Q + LS::Q>(g, 0, x, y, z)];
+      });
+    };
+    auto load_mp = [&](CT* mp) {
+      static_for<0, LS::Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        mp[q] = lam_next[rpull_offset<LS, q, LF::Q + LS::Q>(g, LF::Q, x, y, z)];
+      });
+    };
+    // the F_w seed at this step needs rho and u_x of the gathered state: taken
+    // before the collision's adjoint so that the gathered values need not
+    // stay live through it (block-uniform branch: the block's row has one z)
     const double az = (z == 0) ? a.a0 : ((z == 1) ? a.a1 : 0.0);
+    CT sd_ir = CT(0), sd_ux = CT(0);
     if (az != 0.0) {
       CT drho = CT(0), jx = CT(0);
       static_for<0, LF::Q>([&](auto qc) {
@@ -107,11 +108,21 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(const ST* __restrict__ 
         drho += fg[q];
         if (LF::cx[q]) jx += CT(LF::cx[q]) * fg[q];
       });
-      const CT ir = CT(1) / (CT(1) + drho);
-      const CT ux = jx * ir;
+      sd_ir = CT(1) / (CT(1) + drho);
+      sd_ux = jx * sd_ir;
+    }
+    CT bc = CT(0), bi = CT(0);
+    if constexpr ((MODEL == 0 || MODEL == 2) && PARAM)
+      vjp_cumulant27_param<LS, CT>(fg, ph, load_mg, load_mp, p, gb, pb, bi);
+    else if constexpr (MODEL == 0 || MODEL == 2)
+      vjp_cumulant27<LS, LES, CT>(fg, ph, load_mg, load_mp, p, gb, pb, bc, bi);
+    else
+      vjp_bgk_q19_q6<LES, CT>(fg, ph, load_mg, load_mp, p, gb, pb, bc, bi);
+    // seed of the wall friction term at this step: d u_x / d g_q = (c_qx - u_x) / rho
+    if (az != 0.0) {
       static_for<0, LF::Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
-        gb[q] += CT(az) * (CT(LF::cx[q]) - ux) * ir;
+        gb[q] += CT(az) * (CT(LF::cx[q]) - sd_ux) * sd_ir;
       });
     }
     static_for<0, LF::Q>([&](auto qc) {

@@ -151,6 +151,7 @@ LBM_HD void collide_scalar(CT* ph, CT chi, CT ux, CT uy, CT uz, CT tau, const Ph
     tau_phi = CT(0.5) + (p.d0 + nu_t * p.inv_sct) * p.inv_cs2phi;
   }
   const CT wphi = CT(1) / tau_phi;
+  CT neq[LS::Q];
   static_for<0, LS::Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     constexpr int cx = LS::cx[q], cy = LS::cy[q], cz = LS::cz[q];
@@ -159,7 +160,21 @@ LBM_HD void collide_scalar(CT* ph, CT chi, CT ux, CT uy, CT uz, CT tau, const Ph
     if (cy) cu += CT(cy) * uy;
     if (cz) cu += CT(cz) * uz;
     const CT peq = CT(weight<LS>(q)) * chi * (CT(1) + cu * p.inv_cs2phi);
-    ph[q] = ph[q] - wphi * (ph[q] - peq);
+    neq[q] = ph[q] - peq;
+  });
+  // D3Q6 weights of 1/6 are not exact in binary: rounded, they sum to
+  // 1 + 3e-8 in FP32, and with 1/tau_phi near 2 every collision would raise chi
+  // by about 6e-8 of itself. The non-equilibrium parts sum to zero exactly
+  // (the equilibria sum to chi), so their mean is removed; it leaves the
+  // flux (sum c neq, c in +- pairs) and, before rounding, every value
+  // unchanged. (D3Q7's weights 1/4 and 1/8 are exact.)
+  if constexpr (!LS::has_rest) {
+    const CT mean = tree_sum<0, LS::Q>(neq) * CT(1.0 / LS::Q);
+    static_for<0, LS::Q>([&](auto qc) { neq[decltype(qc)::value] -= mean; });
+  }
+  static_for<0, LS::Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    ph[q] = ph[q] - wphi * neq[q];
   });
 }
 

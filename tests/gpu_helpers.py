@@ -31,6 +31,17 @@ def gpu_moments(lat):
     return {k: v.cpu().numpy() for k, v in m.items()}
 
 
+def component_errors(got, want):
+    """Infinity-norm error of each field against that field's own infinity norm
+    (the plain per-component figure the tests print beside moment_errors)."""
+    out = {}
+    for k in ("rho", "ux", "uy", "uz", "chi"):
+        ref = want[k] - 1.0 if k == "rho" else want[k]
+        scale = np.abs(ref).max()
+        out[k] = float(np.abs(got[k] - want[k]).max() / scale) if scale > 0 else float(np.abs(got[k] - want[k]).max())
+    return out
+
+
 def moment_errors(got, want):
     """Infinity-norm error of each field relative to the oracle field's
     infinity norm: delta rho = rho - 1 for the density, chi, and for every

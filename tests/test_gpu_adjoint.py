@@ -3,7 +3,7 @@
 * 64 x 4 x 8, 200 steps, checkpoints every 50: J, dJ/dC_s, dJ/dSc_T and the
   field dJ/dchi0 against torch autograd through the FP64 oracle, every model,
   the Smagorinsky closure as printed, and the parametrised cumulant with the
-  limiter; FP64 storage to 1e-8 (relative to the largest entry), FP32 to 2e-3.
+  limiter; FP64 storage to 1e-8 (relative to the largest entry), FP32 to 1e-3.
 * 128 x 8 x 16, 500 steps (cumulant, Re_b 1000, C_s 0.1, Sc_T 1): against the
   oracle's FP64 central differences stored in tests/golden (written by
   tests/golden/make_adjoint_fd.py, which calls only the oracle): FP64 to 1e-5,
@@ -70,7 +70,7 @@ def _oracle_ref(i):
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("i", [0, 1, 2, 3, 4, 5], ids=["cumulant", "bgk", "cumulant_fcm", "cumulant_printed_smag",
                                                "parametrised_fcm", "parametrised_cumulant"])
-@pytest.mark.parametrize("storage,tol", [(pkg.F64, 1e-8), (pkg.F32, 2e-3)], ids=["f64", "f32"])
+@pytest.mark.parametrize("storage,tol", [(pkg.F64, 1e-8), (pkg.F32, 1e-3)], ids=["f64", "f32"])
 def test_adjoint_matches_oracle_autograd(i, storage, tol):
     chi0, (J, gcs, gsct, gchi) = _oracle_ref(i)
     gJ, gdcs, gdsct, ggchi = _gpu_grad(TINY[i], storage, chi0, 200, 50)

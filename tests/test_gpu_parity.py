@@ -19,7 +19,7 @@ import paper_2112_08479_amd as pkg
 from oracle import diag as odiag
 from oracle import lbm as olbm
 from tests import inputs
-from tests.gpu_helpers import both, gpu_moments, moment_errors, oracle_moments, ulp
+from tests.gpu_helpers import both, component_errors, gpu_moments, moment_errors, oracle_moments, ulp
 
 pytestmark = pytest.mark.gpu
 
@@ -151,8 +151,10 @@ def test_lock_exchange_fp64_500_steps(model):
     for s in steps:
         lat.step(s - n)
         n = s
-        errs = moment_errors(gpu_moments(lat), ref[s][0])
-        print(f"model {model} step {s} errors {errs}", flush=True)
+        got = gpu_moments(lat)
+        errs = moment_errors(got, ref[s][0])
+        print(f"model {model} step {s} errors {errs}; per own component norm "
+              f"{component_errors(got, ref[s][0])}", flush=True)
         assert max(errs.values()) < 1e-10, (s, errs)
         d, od = lat.diagnostics(), ref[s][1]
         for k in ("mass", "chi_mass", "x_front", "x_f"):
@@ -174,8 +176,10 @@ def test_lock_exchange_fp32_100_steps(model):
     lat = pkg.Lattice(cfg)
     lat.init_lock_exchange(0.125, 1e-3, 0)
     lat.step(100)
-    errs = moment_errors(gpu_moments(lat), ref[100][0])
-    print(f"fp32 model {model} errors {errs}", flush=True)
+    got = gpu_moments(lat)
+    errs = moment_errors(got, ref[100][0])
+    print(f"fp32 model {model} errors {errs}; per own component norm "
+          f"{component_errors(got, ref[100][0])}", flush=True)
     assert max(errs.values()) < 1e-5, errs
 
 

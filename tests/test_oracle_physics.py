@@ -1,10 +1,17 @@
-"""Physics sanity of the oracle itself: the slumping-phase Froude number
-(Eq. 59) of the 128 x 8 x 16 lock exchange at Re_b = 1000, every model,
-against the 0.37 of Table 2 (Case 2, Re_b = 1000), within 0.02.
+"""Physics of the oracle itself (long runs, marked slow: they run when
+LBM_SLOW_TESTS=1 is set).
 
-The run is 4800 FP64 steps (t~ = 12) of the oracle: several minutes on eight
-cores. It is marked slow and runs when LBM_SLOW_TESTS=1 is set; the same
-check runs on the GPU's FP64 path in tests/test_gpu_physics.py.
+* The slumping-phase Froude number (Eq. 59) of the 128 x 8 x 16 lock exchange
+  at Re_b = 1000, every model, against the 0.37 of Table 2 (Case 2), within
+  0.02: 4800 FP64 steps (t~ = 12), several minutes on eight cores. The same
+  check runs on the GPU's FP64 path in tests/test_gpu_physics.py.
+* The instability of model 2 (D3Q19 BGK + Smagorinsky, D3Q6 BGK scalar) at the
+  benchmark's lattice parameters with the standard closure (C_s = 0.1,
+  Sc_T = 1): on 256 x 16 x 32 with the 1024 x 64 x 128 grid's U_b = 0.113 and
+  nu0 = 4.83e-4 (so the same tau0 = tau_phi0 = 0.50145), the oracle's state
+  goes non-finite at t~ = 9.5 after a late exponential growth of max |u|, as
+  the GPU's FP64 path does at the same step. The blow-up is the scheme's, not
+  the kernel's. About five minutes on two cores.
 """
 import os
 
@@ -39,3 +46,27 @@ def test_oracle_froude_number(model):
     fr = odiag.froude_number(ts, xs)
     print(f"oracle model {model}: Fr = {fr:.4f}", flush=True)
     assert abs(fr - 0.37) <= 0.02
+
+
+def test_oracle_model2_standard_closure_goes_unstable_at_re30000_parameters():
+    torch.set_num_threads(os.cpu_count() or 1)
+    ub = (1e-4 * 128) ** 0.5
+    nu0 = ub * 128 / 30000.0
+    cfg = Config(256, 16, 32, model=1, re_b=ub * 32 / nu0, ub_lu=ub, cs_smag=0.1, sc_t=1.0)
+    P = derive(cfg)
+    assert abs(P.tau_phi0 - 0.50145) < 1e-5
+    f, phi = olbm.init_state(P, olbm.chi0_lock_exchange(cfg, 0.125, 1e-3, 0))
+    umax, bad, n = [], None, 0
+    while n < 2800:
+        f, phi = olbm.run(f, phi, P, 20)
+        n += 20
+        d = odiag.diagnostics(f, phi, P, n)
+        if d["nonfinite"] > 0:
+            bad = n
+            break
+        umax.append(d["umax"])
+    print(f"oracle model 2: non-finite at step {bad}; max |u| over the last 100 steps "
+          f"{umax[-5:]}", flush=True)
+    # finite and slow for most of the run, then a fast growth and a blow-up
+    assert bad is not None and 2500 <= bad <= 2800
+    assert max(umax[:100]) < 0.12

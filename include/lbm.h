@@ -237,6 +237,24 @@ int lbm_checkpoint_save(lbm_handle* h, void* dev_slot);
  * may be continued with another C_s, say). Synchronises. */
 int lbm_checkpoint_load(lbm_handle* h, const void* dev_slot);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the diagnostics
+ * of lbm_diagnostics for the state held in a checkpoint slot written by
+ * lbm_checkpoint_save, without a handle or a workspace. cfg must have the
+ * slot's grid, model and storage (LBM_EINVAL otherwise, or if the slot holds
+ * no checkpoint header); its physics parameters (nu0 for F_w, U_b for the
+ * non-dimensional values) are used as given. step, x_f and mass0/chi_mass0
+ * come from the slot's header. The scratch of the diagnostics kernels (span
+ * sums of chi, per-block partial sums, a result slot) is a static device
+ * array of 32 MiB per GPU, held until the process ends: LBM_ENOMEM if the
+ * grid needs more (nx * nz above about 4.1 million). Nothing is allocated.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other host threads, other streams) race and must be serialised by the
+ * caller. hip_stream: the stream to run on (NULL = default); synchronises
+ * it. Returns LBM_EUNSTABLE (with *out filled) if nonfinite > 0. */
+int lbm_checkpoint_diagnostics(const lbm_config* cfg, const void* dev_slot, void* hip_stream,
+                               lbm_diag* out);
+
 /* Test hooks. Pre-collision populations at the current step as full values
  * (f, not f - w), float64, host arrays of q_flow*N and q_scalar*N in the
  * population order above. Synchronous. */

@@ -31,7 +31,7 @@ EXPORTS = [
     "lbm_init_lock_exchange", "lbm_init_from_field", "lbm_step", "lbm_moments",
     "lbm_wall_shear", "lbm_diagnostics", "lbm_get_step", "lbm_checkpoint_save", "lbm_checkpoint_load",
     "lbm_get_populations", "lbm_set_populations", "lbm_adjoint_workspace_bytes",
-    "lbm_adjoint_run", "lbm_stream_copy", "lbm_last_error",
+    "lbm_adjoint_run", "lbm_stream_copy", "lbm_last_error", "lbm_checkpoint_diagnostics",
 ]
 
 
@@ -102,6 +102,7 @@ def lib():
                                                ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                                ctypes.POINTER(dbl), vp]),
             "lbm_last_error": (ctypes.c_char_p, []),
+            "lbm_checkpoint_diagnostics": (ctypes.c_int, [cfgp, vp, vp, ctypes.POINTER(c_diag)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)

@@ -495,6 +495,30 @@ int lbm_get_step(const lbm_handle* h, int64_t* step) {
   return LBM_OK;
 }
 
+// lbm_diag from the diagnostics kernels' result slot r and the initial
+// diagnostics r0 of a run at `step` with gate index x0
+static int fill_diag(lbm_diag* out, const double* r, const double* r0, int64_t step, int x0,
+                     const lbm_config& cfg, const lbm_params& prm) {
+  const double H = (double)cfg.nz, ub = prm.u_b;
+  out->step = step;
+  out->t_nd = (double)step * ub / H;
+  out->mass = r[0];
+  out->mass0 = r0[0];
+  out->chi_mass = r[1];
+  out->chi_mass0 = r0[1];
+  out->fw = r[2];
+  out->fw_nd = ub > 0 ? r[2] / (ub * ub * H * H) : 0.0;
+  out->x_front = r[3];
+  out->x_f = r[3] - x0;
+  out->x_f_nd = out->x_f / H;
+  out->umax = r[4];
+  out->nonfinite = (int64_t)r[5];
+  if (out->nonfinite > 0)
+    return fail(LBM_EUNSTABLE, "%lld nodes hold non-finite moments at step %lld",
+                (long long)out->nonfinite, (long long)step);
+  return LBM_OK;
+}
+
 int lbm_diagnostics(lbm_handle* h, lbm_diag* out) {
   int rc = require_ready(h);
   if (rc) return rc;
@@ -507,24 +531,7 @@ int lbm_diagnostics(lbm_handle* h, lbm_diag* out) {
   HIPCHECK(hipMemcpyAsync(r, h->dres, sizeof(r), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipMemcpyAsync(r0, h->d0, sizeof(r0), hipMemcpyDeviceToHost, h->stream));
   HIPCHECK(hipStreamSynchronize(h->stream));
-  const double H = (double)h->cfg.nz, ub = h->prm.u_b;
-  out->step = h->step;
-  out->t_nd = (double)h->step * ub / H;
-  out->mass = r[0];
-  out->mass0 = r0[0];
-  out->chi_mass = r[1];
-  out->chi_mass0 = r0[1];
-  out->fw = r[2];
-  out->fw_nd = ub > 0 ? r[2] / (ub * ub * H * H) : 0.0;
-  out->x_front = r[3];
-  out->x_f = r[3] - h->x0;
-  out->x_f_nd = out->x_f / H;
-  out->umax = r[4];
-  out->nonfinite = (int64_t)r[5];
-  if (out->nonfinite > 0)
-    return fail(LBM_EUNSTABLE, "%lld nodes hold non-finite moments at step %lld",
-                (long long)out->nonfinite, (long long)h->step);
-  return LBM_OK;
+  return fill_diag(out, r, r0, h->step, h->x0, h->cfg, h->prm);
 }
 
 // Header of a checkpoint slot, in its first 256 bytes (the population buffer
@@ -593,6 +600,70 @@ int lbm_checkpoint_load(lbm_handle* h, const void* dev_slot) {
   h->x0 = hh.x0;
   h->initialised = true;
   return LBM_OK;
+}
+
+int lbm_checkpoint_diagnostics(const lbm_config* cfg, const void* dev_slot, void* hip_stream,
+                               lbm_diag* out) {
+  if (!dev_slot || !out) return fail(LBM_EINVAL, "NULL argument");
+  lbm_params p;
+  int rc = validate(cfg, &p);
+  if (rc) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(LBM_ENODEV, "no GPU visible to the HIP runtime");
+  // scratch of the diagnostics kernels, as a handle's workspace holds it:
+  // span sums of chi, per-block partials, one result slot
+  const Layout L = layout_of(cfg, &p);
+  const size_t n_chibar = align256((size_t)cfg->nx * cfg->nz * sizeof(double)) / sizeof(double);
+  const size_t n_part = align256((size_t)L.diag_blocks * lbm::kDiagSlots * sizeof(double)) / sizeof(double);
+  const size_t need = n_chibar + n_part + 32;
+  if (need > lbm::kStaticScratchDoubles)
+    return fail(LBM_ENOMEM, "the diagnostics of a %d x %d x %d grid need %zu bytes of scratch; the "
+                "allocation-free entry point holds %zu (nx * nz up to about %zu)", cfg->nx, cfg->ny,
+                cfg->nz, need * sizeof(double), lbm::kStaticScratchDoubles * sizeof(double),
+                lbm::kStaticScratchDoubles - n_part - 32);
+  double* sp = nullptr;
+  HIPCHECK(lbm::static_scratch(&sp));
+  hipStream_t stream = (hipStream_t)hip_stream;
+  const char* hdr = (const char*)dev_slot;
+  CkptHeader hh;
+  HIPCHECK(hipMemcpyAsync(&hh, hdr, sizeof(hh), hipMemcpyDeviceToHost, stream));
+  HIPCHECK(hipStreamSynchronize(stream));
+  if (hh.magic != kCkptMagic)
+    return fail(LBM_EINVAL, "slot does not hold a checkpoint (bad header)");
+  if (hh.nx != cfg->nx || hh.ny != cfg->ny || hh.nz != cfg->nz || hh.model != cfg->model ||
+      hh.storage != cfg->storage)
+    return fail(LBM_EINVAL, "checkpoint of a %d x %d x %d grid, model %d, storage %d does not match "
+                "the configuration's %d x %d x %d, model %d, storage %d", hh.nx, hh.ny, hh.nz, hh.model,
+                hh.storage, cfg->nx, cfg->ny, cfg->nz, cfg->model, cfg->storage);
+  // a handle on the host stack (no device memory of its own): the slot's
+  // populations and the static scratch
+  lbm_handle t{};
+  t.cfg = *cfg;
+  t.prm = p;
+  t.qf = p.q_flow;
+  t.qs = p.q_scalar;
+  t.qt = p.q_flow + p.q_scalar;
+  t.n = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+  t.esize = storage_bytes(cfg->storage);
+  t.state_bytes = state_bytes_of(cfg, t.qt);
+  HIPCHECK(hipGetDevice(&t.device));
+  t.stream = stream;
+  t.buf[0] = (void*)(hdr + kCkptHeaderBytes);
+  t.buf[1] = nullptr;
+  t.cur = 0;
+  t.chibar = sp;
+  t.partials = sp + n_chibar;
+  t.dres = sp + n_chibar + n_part;
+  t.diag_blocks = L.diag_blocks;
+  t.step = hh.step;
+  t.x0 = hh.x0;
+  t.initialised = true;
+  HIPCHECK(lbm::launch_diag(&t, t.dres));
+  double r[8];
+  HIPCHECK(hipMemcpyAsync(r, t.dres, sizeof(r), hipMemcpyDeviceToHost, stream));
+  HIPCHECK(hipStreamSynchronize(stream));
+  return fill_diag(out, r, hh.d0, hh.step, hh.x0, *cfg, p);
 }
 
 int lbm_get_populations(lbm_handle* h, double* host_f, double* host_phi) {

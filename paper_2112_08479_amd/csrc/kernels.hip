@@ -12,6 +12,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "collide.h"
 #include "lattice.h"
@@ -572,6 +573,35 @@ __global__ __launch_bounds__(kBlock) void k_set_pop(ST* __restrict__ dst, Grid g
     if ((unsigned)xs >= (unsigned)g.nx || (unsigned)zs >= (unsigned)g.nz)
       put(elem_index<LF::Q + LS::Q>(g, base + o, row, x), v[node] - w);
   }
+}
+
+// ------------------------------------------- allocation-free diagnostics
+// Scratch of lbm_checkpoint_diagnostics: the span-averaged concentration, the
+// per-block partial sums and the result slot of the diagnostics kernels,
+// which a handle keeps in its workspace. A file-scope device array, so that
+// the entry point allocates nothing; every GPU the library runs on holds its
+// own copy until the process ends. In host code its name is only a stand-in
+// for the symbol: its device address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is used.
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+hipError_t static_scratch(double** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------- dispatch

@@ -75,6 +75,10 @@ hipError_t launch_get_pop(lbm_handle* h, int q, double* dst);
 hipError_t launch_set_pop(lbm_handle* h, int q, const double* src);
 hipError_t launch_copy_state(lbm_handle* h, const void* src, void* dst);
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+// device address, on the current device, of the static scratch array of the
+// allocation-free diagnostics (kStaticScratchDoubles doubles)
+constexpr size_t kStaticScratchDoubles = (size_t)1 << 22;
+hipError_t static_scratch(double** ptr);
 
 // adjoint.hip
 int adjoint_blocks(const lbm_handle* h);

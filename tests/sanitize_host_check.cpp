@@ -33,6 +33,7 @@ hipError_t launch_fw_layers(lbm_handle*, const void*, double*) { return hipError
 hipError_t launch_fw_reduce(lbm_handle*, const double*, int64_t, double*) { return hipErrorNoDevice; }
 hipError_t launch_sum_pairs(lbm_handle*, const double*, int, double*) { return hipErrorNoDevice; }
 hipError_t launch_zero(lbm_handle*, double*, int64_t) { return hipErrorNoDevice; }
+hipError_t static_scratch(double**) { return hipErrorNoDevice; }
 }  // namespace lbm
 
 static int fails = 0;
@@ -143,6 +144,12 @@ int main() {
   EXPECT(lbm_stream_copy((void*)256, (void*)512, 17, nullptr) == LBM_EINVAL);
   double J, a, b;
   EXPECT(lbm_adjoint_run(nullptr, 10, 5, 1.0, 1.0, nullptr, 0, &J, &a, &b, nullptr) == LBM_EINVAL);
+  EXPECT(lbm_checkpoint_diagnostics(nullptr, nullptr, nullptr, &d) == LBM_EINVAL);
+  {
+    lbm_config c = base(64, 4, 8, 0, LBM_F32);
+    const int rc = lbm_checkpoint_diagnostics(&c, (void*)256, nullptr, &d);
+    EXPECT(rc == LBM_ENODEV || rc == LBM_EDEVICE);
+  }
   EXPECT(lbm_destroy(nullptr) == LBM_OK);
   printf("fails %d\nsanitize ok\n", fails);
   return fails != 0;

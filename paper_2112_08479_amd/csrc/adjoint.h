@@ -16,15 +16,6 @@
 
 namespace lbm {
 
-// Keeps the instruction scheduler from moving work across this point (device
-// code; no effect on the host). The adjoints of the post-collision values are
-// loaded behind it, where the chain rule first needs them, so that they are
-// not held in registers through the forward recompute.
-LBM_HD void sched_fence() {
-#if defined(__HIP_DEVICE_COMPILE__)
-  __builtin_amdgcn_sched_barrier(0);
-#endif
-}
 
 // adjoint of inv1d (linear in o2, so o2's own value is not needed)
 template <typename CT>
@@ -281,8 +272,8 @@ LBM_HD void flow_moments_vjp(CT bdrho, CT bjx, CT bjy, CT bjz, CT bpxx, CT bpyy,
 
 // ---- cumulant D3Q27 + scalar lattice LS (D3Q7 BGK or D3Q27 FCM),
 // omega3..omega6 = 1
-template <class LS, bool LES, typename CT, class LoadMG, class LoadMP>
-LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, LoadMG&& load_mg, LoadMP&& load_mp,
+template <class LS, bool LES, typename CT>
+LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, const CT* mg, const CT* mp,
                            const Phys<CT>& p, CT* gb, CT* pb, CT& b_cles, CT& b_isct) {
   // ---- forward recompute
   CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
@@ -346,14 +337,10 @@ LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, LoadMG&& load_mg, LoadMP&&
   // ---- reverse
   CT bchi = CT(0), bux = CT(0), buy = CT(0), buz = CT(0), btau = CT(0);
   CT buzs = CT(0);
-  CT mp[LS::Q], mg[27];
-  sched_fence();
-  load_mp(mp);
   scalar_collision_vjp<LS, LES, CT>(ph, chi, ux, uy, uzs, tau, p, mp, pb, bchi, bux, buy, buzs, btau,
                                     b_isct);
   CT mb[27];
   CT bvz = CT(0);
-  load_mg(mg);
   inverse_chimera_vjp<CT>(m, ux, uy, vz, mg, mb, bux, buy, bvz);
   CT brho = CT(0), bdrho = CT(0);
   CT bexx = CT(0), beyy = CT(0), bezz = CT(0), bexy = CT(0), bexz = CT(0), beyz = CT(0);
@@ -442,8 +429,8 @@ LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, LoadMG&& load_mg, LoadMP&&
 // derivative of collide_cumulant27_param. The limited third-order map
 // X -> X (1 - w)(1 - |X| / (|X| + lambda)) has the derivative
 // (1 - w)(1 - q)^2, q = |X| / (|X| + lambda), which is smooth at X = 0.
-template <class LS, typename CT, class LoadMG, class LoadMP>
-LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, LoadMG&& load_mg, LoadMP&& load_mp,
+template <class LS, typename CT>
+LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, const CT* mg, const CT* mp,
                                  const Phys<CT>& p, CT* gb, CT* pb, CT& b_isct) {
   // ---- forward recompute (as collide_cumulant27_param)
   CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
@@ -536,14 +523,10 @@ LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, LoadMG&& load_mg, Lo
 
   // ---- reverse
   CT bchi = CT(0), bux = CT(0), buy = CT(0), buz = CT(0), btau = CT(0), buzs = CT(0);
-  CT mp[LS::Q], mg[27];
-  sched_fence();
-  load_mp(mp);
   scalar_collision_vjp<LS, false, CT>(ph, chi, ux, uy, uzs, p.tau0, p, mp, pb, bchi, bux, buy, buzs,
                                       btau, b_isct);
   CT mb[27];
   CT bvz = CT(0);
-  load_mg(mg);
   inverse_chimera_vjp<CT>(m, ux, uy, vz, mg, mb, bux, buy, bvz);
   CT brho = CT(0), bdrho = mb[0];
   CT r[27];
@@ -693,8 +676,8 @@ LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, LoadMG&& load_mg, Lo
 }
 
 // ---- BGK D3Q19 + Guo + Smagorinsky, D3Q6 scalar
-template <bool LES, typename CT, class LoadMG, class LoadMP>
-LBM_HD void vjp_bgk_q19_q6(const CT* g, const CT* ph, LoadMG&& load_mg, LoadMP&& load_mp, const Phys<CT>& p,
+template <bool LES, typename CT>
+LBM_HD void vjp_bgk_q19_q6(const CT* g, const CT* ph, const CT* mg, const CT* mp, const Phys<CT>& p,
                            CT* gb, CT* pb, CT& b_cles, CT& b_isct) {
   CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
   flow_moments<Q19>(g, drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz);
@@ -722,11 +705,7 @@ LBM_HD void vjp_bgk_q19_q6(const CT* g, const CT* ph, LoadMG&& load_mg, LoadMP&&
   const CT sfac = CT(1) - CT(0.5) * w;
 
   CT bchi = CT(0), bux = CT(0), buy = CT(0), buz = CT(0), btau = CT(0);
-  CT mp[6], mg[19];
-  sched_fence();
-  load_mp(mp);
   scalar_vjp<Q6, LES, CT>(ph, chi, ux, uy, uz, tau, p, mp, pb, bchi, bux, buy, buz, btau, b_isct);
-  load_mg(mg);
   CT bw = CT(0), bsfac = CT(0), busq = CT(0), bdrho = CT(0), brho = CT(0), bFz = CT(0);
   static_for<0, 19>([&](auto qc) {
     constexpr int q = decltype(qc)::value;

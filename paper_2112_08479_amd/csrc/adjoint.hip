@@ -42,23 +42,6 @@ struct AModel<2> {
   using LS = Q27;
 };
 
-// reverse pull of the adjoint: slot of lambda that population q at node
-// (x, y, z) receives from (lambda buffers use the population buffers'
-// x-blocked layout, QT populations)
-template <class L, int q, int QT>
-__device__ __forceinline__ int64_t rpull_offset(const Grid& g, int base, int x, int y, int z) {
-  constexpr int cx = L::cx[q], cy = L::cy[q], cz = L::cz[q];
-  const int xn = x + cx, zn = z + cz;
-  int yn = y + cy;
-  if (cy == -1) yn = (y == 0) ? g.ny - 1 : yn;
-  if (cy == 1) yn = (y == g.ny - 1) ? 0 : yn;
-  bool wall = false;
-  if (cx != 0) wall = wall || ((unsigned)xn >= (unsigned)g.nx);
-  if (cz != 0) wall = wall || ((unsigned)zn >= (unsigned)g.nz);
-  return wall ? elem_index<QT>(g, base + opp<L>(q), (int64_t)z * g.ny + y, x)
-              : elem_index<QT>(g, base + q, (int64_t)zn * g.ny + yn, xn);
-}
-
 struct AdjStep {
   double a0, a1;        // F_w seed coefficients at z = 0 and z = 1 (0 when not seeded)
   double dcs_dc;        // d c_les / d C_s: 36 sqrt(2) C_s, or 18 sqrt(2) in the printed form
@@ -74,64 +57,70 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(const ST* __restrict__ 
                                                          Phys<CT> p, AdjStep a, int nbx) {
   using LF = typename AModel<MODEL>::LF;
   using LS = typename AModel<MODEL>::LS;
-  const int b = blockIdx.x;
+  constexpr int QT = LF::Q + LS::Q;
+  // a row's tiles on one XCD, as in the step kernel: the pulls across tile
+  // edges then find the neighbouring tile's lines in the same L2
+  const int b = xcd_row_order(blockIdx.x, gridDim.x, nbx);
   const int row = b / nbx;
-  const int x = (b - row * nbx) * blockDim.x + threadIdx.x;
-  double v[2] = {0.0, 0.0};
-  if (x < g.nx) {
-    const int y = row % g.ny, z = row / g.ny;
-    const int64_t node = (int64_t)row * g.nx + x;
-    CT fg[LF::Q], ph[LS::Q], gb[LF::Q], pb[LS::Q];
-    gather<LF, LS, ST, CT>(state, g, x, y, z, fg, ph);
-    // reverse pulls of lambda(m + 1), made where the collision's adjoint needs them
-    auto load_mg = [&](CT* mg) {
-      static_for<0, LF::Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        mg[q] = lam_next[rpull_offset<LF, q, LF::Q + LS::Q>(g, 0, x, y, z)];
-      });
-    };
-    auto load_mp = [&](CT* mp) {
-      static_for<0, LS::Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        mp[q] = lam_next[rpull_offset<LS, q, LF::Q + LS::Q>(g, LF::Q, x, y, z)];
-      });
-    };
-    // the F_w seed at this step needs rho and u_x of the gathered state: taken
-    // before the collision's adjoint so that the gathered values need not
-    // stay live through it (block-uniform branch: the block's row has one z)
-    const double az = (z == 0) ? a.a0 : ((z == 1) ? a.a1 : 0.0);
-    CT sd_ir = CT(0), sd_ux = CT(0);
-    if (az != 0.0) {
-      CT drho = CT(0), jx = CT(0);
-      static_for<0, LF::Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        drho += fg[q];
-        if (LF::cx[q]) jx += CT(LF::cx[q]) * fg[q];
-      });
-      sd_ir = CT(1) / (CT(1) + drho);
-      sd_ux = jx * sd_ir;
-    }
-    CT bc = CT(0), bi = CT(0);
-    if constexpr ((MODEL == 0 || MODEL == 2) && PARAM)
-      vjp_cumulant27_param<LS, CT>(fg, ph, load_mg, load_mp, p, gb, pb, bi);
-    else if constexpr (MODEL == 0 || MODEL == 2)
-      vjp_cumulant27<LS, LES, CT>(fg, ph, load_mg, load_mp, p, gb, pb, bc, bi);
-    else
-      vjp_bgk_q19_q6<LES, CT>(fg, ph, load_mg, load_mp, p, gb, pb, bc, bi);
-    // seed of the wall friction term at this step: d u_x / d g_q = (c_qx - u_x) / rho
-    if (az != 0.0) {
-      static_for<0, LF::Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        gb[q] += CT(az) * (CT(LF::cx[q]) - sd_ux) * sd_ir;
-      });
-    }
+  const int x0 = (b - row * nbx) * (int)blockDim.x;
+  const int y = row % g.ny, z = row / g.ny;
+  // The step kernel's addressing: block-uniform row segments (scalar
+  // registers) plus the lane's own, x - 1 and x + 1 offsets. Lanes past the
+  // row's end read its last node (their results are dropped), so that every
+  // lane takes part in the loads and in the x-wall fix-up's wave ballot.
+  const TileLanes<QT, 1> t = tile_lanes<QT, 1>(g, x0, (int)threadIdx.x, (int)blockDim.x);
+  const int x = t.x[0];
+  const bool active = x < g.nx;
+  CT fg1[1][LF::Q], ph1[1][LS::Q], gb[LF::Q], pb[LS::Q];
+  gather_rows<LF, LS, 1, ST, CT>(state, g, t, y, z, fg1, ph1);
+  const CT* fg = fg1[0];
+  const CT* ph = ph1[0];
+  const bool wave_at_wall = __builtin_amdgcn_ballot_w64(x == 0 || x == g.nx - 1) != 0;
+  // reverse pulls of lambda(m + 1) (the pull on the reversed velocities),
+  // issued with the state's loads so that their latencies overlap (the
+  // register allocation is the same either way)
+  CT lg[1][LF::Q], lp[1][LS::Q];
+  pull_lattice<Rev<LF>, 0, QT, 1, CT, CT>(lam_next, g, y, z, t, wave_at_wall, lg);
+  pull_lattice<Rev<LS>, LF::Q, QT, 1, CT, CT>(lam_next, g, y, z, t, wave_at_wall, lp);
+  // the F_w seed at this step needs rho and u_x of the gathered state: taken
+  // before the collision's adjoint so that the gathered values need not
+  // stay live through it (block-uniform branch: the block's row has one z)
+  const double az = (z == 0) ? a.a0 : ((z == 1) ? a.a1 : 0.0);
+  CT sd_ir = CT(0), sd_ux = CT(0);
+  if (az != 0.0) {
+    CT drho = CT(0), jx = CT(0);
     static_for<0, LF::Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      lam_out[elem_index<LF::Q + LS::Q>(g, q, row, x)] = gb[q];
+      drho += fg[q];
+      if (LF::cx[q]) jx += CT(LF::cx[q]) * fg[q];
+    });
+    sd_ir = CT(1) / (CT(1) + drho);
+    sd_ux = jx * sd_ir;
+  }
+  CT bc = CT(0), bi = CT(0);
+  if constexpr ((MODEL == 0 || MODEL == 2) && PARAM)
+    vjp_cumulant27_param<LS, CT>(fg, ph, lg[0], lp[0], p, gb, pb, bi);
+  else if constexpr (MODEL == 0 || MODEL == 2)
+    vjp_cumulant27<LS, LES, CT>(fg, ph, lg[0], lp[0], p, gb, pb, bc, bi);
+  else
+    vjp_bgk_q19_q6<LES, CT>(fg, ph, lg[0], lp[0], p, gb, pb, bc, bi);
+  // seed of the wall friction term at this step: d u_x / d g_q = (c_qx - u_x) / rho
+  if (az != 0.0) {
+    static_for<0, LF::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      gb[q] += CT(az) * (CT(LF::cx[q]) - sd_ux) * sd_ir;
+    });
+  }
+  double v[2] = {0.0, 0.0};
+  if (active) {
+    CT* orow = lam_out + (int64_t)row * g.nxb * (QT * kXB);
+    static_for<0, LF::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      orow[q * kXB + t.own[0]] = gb[q];
     });
     static_for<0, LS::Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
-      lam_out[elem_index<LF::Q + LS::Q>(g, LF::Q + q, row, x)] = pb[q];
+      orow[(LF::Q + q) * kXB + t.own[0]] = pb[q];
     });
     if (a.dchi0) {
       double s = 0.0;
@@ -139,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(const ST* __restrict__ 
         constexpr int q = decltype(qc)::value;
         s += weight<LS>(q) * (double)pb[q];
       });
-      a.dchi0[node] = s;
+      a.dchi0[(int64_t)row * g.nx + x] = s;
     }
     v[0] = (double)bc * a.dcs_dc;
     v[1] = (double)bi * a.disct_dsct;

@@ -45,18 +45,10 @@ LBM_HD double to_d<double>(double v) { return v; }
 template <>
 LBM_HD double to_d<float>(float v) { return (double)v; }
 
-#ifndef LBM_NT_STORE
-#define LBM_NT_STORE 1
-#endif
-#ifndef LBM_XCD_REMAP
-#define LBM_XCD_REMAP 2
-#endif
-
 // Post-collision values are not read again before the next launch, so they
-// may bypass the caches on the way to HBM.
+// may bypass the caches on the way to HBM (plain stores measured 5 % slower).
 template <typename ST>
 __device__ __forceinline__ void store_val(ST* p, ST v) {
-#if LBM_NT_STORE
   if constexpr (std::is_same<ST, double>::value || std::is_same<ST, float>::value) {
     __builtin_nontemporal_store(v, p);
   } else {
@@ -64,49 +56,9 @@ __device__ __forceinline__ void store_val(ST* p, ST v) {
     __builtin_memcpy(&bits, &v, 2);
     __builtin_nontemporal_store(bits, reinterpret_cast<uint16_t*>(p));
   }
-#else
-  *p = v;
-#endif
-}
-
-// Block order. Consecutive block ids are dealt round-robin to the 8 XCDs
-// (each with its own L2). The tiles of one row share a cache line at each
-// tile edge (the x-shifted pulls read one element across it).
-//   LBM_XCD_REMAP 1: every XCD works on a contiguous range of tiles.
-//   LBM_XCD_REMAP 2 (default): rows in groups of eight; within a group,
-//     block b takes row b % 8 and tile b / 8 of it, so a whole row runs on
-//     one XCD with its tiles dispatched eight blocks apart, while consecutive
-//     blocks still go to different rows (a tail group of fewer rows is dealt
-//     the same way). Measured against plain order: FP16 +3.7 %, FP32 within
-//     1 %, and less read traffic at tile edges.
-//   LBM_XCD_REMAP 0: plain order.
-__device__ __forceinline__ int block_order(int b, int nblocks, int nbx) {
-#if LBM_XCD_REMAP == 1
-  (void)nbx;
-  constexpr int kXcd = 8;
-  const int per = nblocks / kXcd;
-  if (b >= per * kXcd) return b;
-  return (b % kXcd) * per + b / kXcd;
-#elif LBM_XCD_REMAP == 2
-  constexpr int kXcd = 8;
-  const int group = kXcd * nbx;                 // tiles of eight rows
-  const int g0 = b / group, rem = b - g0 * group;
-  const int nrows = nblocks / nbx;
-  const int rows = min(kXcd, nrows - g0 * kXcd);  // rows in this group
-  const int i = rem / rows, r = g0 * kXcd + (rem - (rem / rows) * rows);
-  return r * nbx + i;
-#else
-  (void)nblocks;
-  (void)nbx;
-  return b;
-#endif
 }
 
 // ------------------------------------------------------------------- step
-#ifndef LBM_PERSIST
-#define LBM_PERSIST 0
-#endif
-
 // collision kinds of the cumulant models
 enum { kCumFast = 0, kCumGeneral = 1, kCumParam = 2 };
 
@@ -188,24 +140,13 @@ __device__ __forceinline__ void step_tile(const ST* __restrict__ src, ST* __rest
   });
 }
 
-// minimum waves per SIMD requested from the register allocator (0: none)
-#ifndef LBM_STEP_WAVES
-#define LBM_STEP_WAVES 0
-#endif
-
 template <int MODEL, typename ST, typename SS, typename CT, bool LES, int KIND, int NPT,
           bool FW = false>
-__global__ __launch_bounds__(kBlock, LBM_STEP_WAVES) void k_step(const ST* __restrict__ src, ST* __restrict__ dst,
-                                                 Grid g, Phys<CT> p, int nbx, int ntiles,
+__global__ __launch_bounds__(kBlock) void k_step(const ST* __restrict__ src, ST* __restrict__ dst,
+                                                 Grid g, Phys<CT> p, int nbx,
                                                  double* __restrict__ fwp) {
-#if LBM_PERSIST
-  for (int b = blockIdx.x; b < ntiles; b += gridDim.x)
-    step_tile<MODEL, ST, SS, CT, LES, KIND, NPT, FW>(src, dst, g, p, nbx, b, fwp);
-#else
-  (void)ntiles;
   step_tile<MODEL, ST, SS, CT, LES, KIND, NPT, FW>(src, dst, g, p, nbx,
-                                                   block_order(blockIdx.x, gridDim.x, nbx), fwp);
-#endif
+                                                   xcd_row_order(blockIdx.x, gridDim.x, nbx), fwp);
 }
 
 // ------------------------------------------------------------ init states
@@ -679,12 +620,7 @@ static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src,
   const int per_thread_x = (g.nx + NPT - 1) / NPT;  // x-extent in threads if one block
   const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
   const int nbx = (g.nx + bx * NPT - 1) / (bx * NPT);
-  const int ntiles = (int)((int64_t)nbx * g.ny * g.nz);
-#if LBM_PERSIST
-  const unsigned blocks = (unsigned)std::min<int64_t>(ntiles, (int64_t)256 * LBM_PERSIST);
-#else
-  const unsigned blocks = (unsigned)ntiles;
-#endif
+  const unsigned blocks = (unsigned)((int64_t)nbx * g.ny * g.nz);
   const Phys<CT> p = phys_of<CT>(h);
   const ST* s = static_cast<const ST*>(src);
   ST* d = static_cast<ST*>(dst);
@@ -694,14 +630,14 @@ static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src,
       if (kind == kCumGeneral) return hipErrorInvalidValue;
       if constexpr (M != 1) {
         if (kind == kCumParam) {
-          hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumParam, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, fw);
+          hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumParam, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, fw);
           return hipGetLastError();
         }
       }
       if (les)
-        hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, fw);
+        hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, fw);
       else
-        hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, fw);
+        hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, fw);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
@@ -709,22 +645,22 @@ static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src,
   }
   if constexpr (M == 1) {  // BGK: one collision kind
     if (les)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
     else
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
   } else {
     // the parametrised kind never has the LES (rejected when the handle is made)
     const int kind = cumulant_kind(h);
     if (les && kind == kCumGeneral)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
     else if (les)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
     else if (kind == kCumParam)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumParam, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumParam, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
     else if (kind == kCumGeneral)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
     else
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, ntiles, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
   }
   return hipGetLastError();
 }

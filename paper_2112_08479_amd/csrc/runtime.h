@@ -36,27 +36,15 @@ struct lbm_handle {
 
 namespace lbm {
 
-#ifndef LBM_BLOCK
-#define LBM_BLOCK 256
-#endif
-constexpr int kBlock = LBM_BLOCK;  // threads per block along x (multiple of 64)
-#ifndef LBM_NPT
-#define LBM_NPT 2
-#endif
-constexpr int kNodesPerThread = LBM_NPT;  // step kernel: nodes per thread along x
-#ifndef LBM_NPT_FCM
-#define LBM_NPT_FCM 1
-#endif
-#ifndef LBM_NPT16
-#define LBM_NPT16 1
-#endif
+constexpr int kBlock = 256;  // threads per block along x (multiple of 64)
+constexpr int kNodesPerThread = 2;  // step kernel: nodes per thread along x (FP32, FP64)
 // The cumulant + D3Q27-scalar model holds 54 populations per node: one node
 // per thread keeps its register count (and so its occupancy) near the others'.
 // With 16-bit storage one node per thread also measured faster (FP16 +5 %,
 // BF16 +13 % at 2048 x 128 x 256); FP32 is faster at two.
 template <int MODEL, typename ST>
 constexpr int nodes_per_thread() {
-  return MODEL == 2 ? LBM_NPT_FCM : (sizeof(ST) == 2 ? LBM_NPT16 : kNodesPerThread);
+  return MODEL == 2 ? 1 : (sizeof(ST) == 2 ? 1 : kNodesPerThread);
 }
 constexpr int kDiagSlots = 8;  // partial sums per diagnostic block
 

@@ -67,6 +67,49 @@ void check(int nx, int ny, int nz, int kBlock) {
   for (char c : stored) cnt += c;
   if (cnt != (long)QT * nx * ny * nz) { ++fails; printf("store count %ld vs %ld (%d %d %d)\n", cnt, (long)QT * nx * ny * nz, nx, ny, nz); }
 }
+// The adjoint's reverse pull of lambda: pull_lattice on Rev<L> (the step
+// kernel's segments and lane offsets with the velocities reversed) in the
+// adjoint step's geometry (one node per thread), against the reverse pull
+// written out here: population q at node x receives slot (q, x + c_q) when
+// x + c_q is a fluid node (y periodic), else slot (opp q, x).
+template <class L, int base, int QT>
+void check_rev(int nx, int ny, int nz, int bx) {
+  Grid g{nx, ny, nz, (int64_t)nx * ny * nz, xblocks(nx)};
+  const int64_t total = (int64_t)ny * nz * g.nxb * QT * kXB;
+  const int nbx = (nx + bx - 1) / bx;
+  for (int row = 0; row < ny * nz; ++row) {
+    const int y = row % ny, z = row / ny;
+    for (int tb = 0; tb < nbx; ++tb)
+      for (int tid = 0; tid < bx; ++tid) {
+        const int x0 = tb * bx;
+        auto t = tile_lanes<QT, 1>(g, x0, tid, bx);
+        static_for<0, L::Q>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          bool zw;
+          const int64_t seg = pull_segment<Rev<L>, q, base, QT>(g, y, z, zw);
+          const int64_t idx = seg + pull_lane<Rev<L>, q, QT, 1>(t, 0, zw);
+          const int64_t bidx = bounce_segment<Rev<L>, q, base, QT>(g, y, z) + t.own[0];
+          if (idx < 0 || idx >= total || bidx < 0 || bidx >= total) {
+            ++fails;
+            if (fails < 10) printf("rev OOB %d %d %d q%d\n", nx, ny, nz, q);
+          }
+          const int x = t.x[0];
+          if (x >= nx) return;  // lane past the row's end: result dropped
+          const int64_t eff = x_wall<Rev<L>, q>(g, x, zw) ? bidx : idx;
+          const int xn = x + L::cx[q], zn = z + L::cz[q];
+          const int yn = ((y + L::cy[q]) % ny + ny) % ny;
+          const bool fluid = xn >= 0 && xn < nx && zn >= 0 && zn < nz;
+          const int64_t ref = fluid ? elem_index<QT>(g, base + q, (int64_t)zn * ny + yn, xn)
+                                    : elem_index<QT>(g, base + opp<L>(q), (int64_t)row, x);
+          if (eff != ref) {
+            ++fails;
+            if (fails < 10) printf("rev mismatch %d %d %d row %d x %d q %d\n", nx, ny, nz, row, x, q);
+          }
+        });
+      }
+  }
+}
+
 int main() {
   const int nxs[] = {1, 2, 5, 63, 64, 65, 127, 128, 129, 300, 513, 1024};
   const int ns[] = {1, 2, 3, 4};
@@ -78,6 +121,13 @@ int main() {
         check<Q19, Q6, 1>(nx, ny, nz, 256);
         check<Q27, Q27, 1>(nx, ny, nz, 256);
         check<Q27, Q7, 1>(nx, ny, nz, 64);
+        for (int bx : {64, 256}) {
+          check_rev<Q27, 0, 34>(nx, ny, nz, bx);
+          check_rev<Q7, 27, 34>(nx, ny, nz, bx);
+          check_rev<Q19, 0, 25>(nx, ny, nz, bx);
+          check_rev<Q6, 19, 25>(nx, ny, nz, bx);
+          check_rev<Q27, 27, 54>(nx, ny, nz, bx);
+        }
       }
   printf("fails %ld\n", fails);
   return fails != 0;

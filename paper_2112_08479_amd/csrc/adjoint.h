@@ -429,8 +429,13 @@ LBM_HD void vjp_cumulant27(const CT* g, const CT* ph, const CT* mg, const CT* mp
 // derivative of collide_cumulant27_param. The limited third-order map
 // X -> X (1 - w)(1 - |X| / (|X| + lambda)) has the derivative
 // (1 - w)(1 - q)^2, q = |X| / (|X| + lambda), which is smooth at X = 0.
-template <class LS, typename CT>
-LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, const CT* mg, const CT* mp,
+// Without the LES the scalar collision's adjoint and the flow's reverse
+// sweep meet only in additive accumulators (the velocity and chi adjoints),
+// so the scalar part runs last: the caller passes chi = sum of ph, and
+// reload(ph, mp) fills the scalar populations and their adjoints only when
+// they are needed, so that they need not be held through the flow part.
+template <class LS, typename CT, class Reload>
+LBM_HD void vjp_cumulant27_param(const CT* g, CT chi, const CT* mg, Reload&& reload,
                                  const Phys<CT>& p, CT* gb, CT* pb, CT& b_isct) {
   // ---- forward recompute (as collide_cumulant27_param)
   CT drho, jx, jy, jz, pxx, pyy, pzz, pxy, pxz, pyz;
@@ -439,7 +444,6 @@ LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, const CT* mg, const 
   third_raw_sums<CT>(g, r3);
   const CT r120 = r3[0], r102 = r3[1], r210 = r3[2], r012 = r3[3], r201 = r3[4], r021 = r3[5],
            r111 = r3[6];
-  const CT chi = scalar_sum<LS>(ph);
   const CT rho = CT(1) + drho;
   const CT ir = CT(1) / rho;
   const CT Fz = -p.g * chi;
@@ -522,9 +526,7 @@ LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, const CT* mg, const 
   const CT uzs = (jz + CT(0.5) * Fz) * ir;
 
   // ---- reverse
-  CT bchi = CT(0), bux = CT(0), buy = CT(0), buz = CT(0), btau = CT(0), buzs = CT(0);
-  scalar_collision_vjp<LS, false, CT>(ph, chi, ux, uy, uzs, p.tau0, p, mp, pb, bchi, bux, buy, buzs,
-                                      btau, b_isct);
+  CT bchi = CT(0), bux = CT(0), buy = CT(0), buz = CT(0), buzs = CT(0);
   CT mb[27];
   CT bvz = CT(0);
   inverse_chimera_vjp<CT>(m, ux, uy, vz, mg, mb, bux, buy, bvz);
@@ -648,6 +650,13 @@ LBM_HD void vjp_cumulant27_param(const CT* g, const CT* ph, const CT* mg, const 
   bux -= CT(2) * ux * bdxx + uy * bdxy + uz * bdxz;
   buy -= CT(2) * uy * bdyy + ux * bdxy + uz * bdyz;
   buz -= CT(2) * uz * bdzz + ux * bdxz + uy * bdyz;
+  // the scalar collision
+  {
+    CT phr[LS::Q], mpr[LS::Q], btau = CT(0);
+    reload(phr, mpr);
+    scalar_collision_vjp<LS, false, CT>(phr, chi, ux, uy, uzs, p.tau0, p, mpr, pb, bchi, bux, buy,
+                                        buzs, btau, b_isct);
+  }
   // velocities
   CT bjx = bux * ir, bjy = buy * ir, bjz = buz * ir;
   bir += bux * jx + buy * jy + buz * jz;

@@ -98,9 +98,32 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(const ST* __restrict__ 
     sd_ux = jx * sd_ir;
   }
   CT bc = CT(0), bi = CT(0);
-  if constexpr ((MODEL == 0 || MODEL == 2) && PARAM)
-    vjp_cumulant27_param<LS, CT>(fg, ph, lg[0], lp[0], p, gb, pb, bi);
-  else if constexpr (MODEL == 0 || MODEL == 2)
+  if constexpr ((MODEL == 0 || MODEL == 2) && PARAM) {
+    // the scalar populations and their adjoints wait in LDS, each thread in
+    // its own column, while the flow's reverse sweep runs (the adjoint
+    // above takes them last): that keeps the kernel at two waves per SIMD
+    __shared__ CT stash[2 * LS::Q][kBlock];
+    const int tid = (int)threadIdx.x;
+    const CT chi = scalar_sum<LS>(ph);
+    static_for<0, LS::Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      stash[q][tid] = ph[q];
+      stash[LS::Q + q][tid] = lp[0][q];
+    });
+    vjp_cumulant27_param<LS, CT>(
+        fg, chi, lg[0],
+        [&](CT* phr, CT* mpr) {
+          // a compiler barrier: the values are read back from LDS here, not
+          // forwarded from the registers that wrote them
+          asm volatile("" ::: "memory");
+          static_for<0, LS::Q>([&](auto qc) {
+            constexpr int q = decltype(qc)::value;
+            phr[q] = stash[q][tid];
+            mpr[q] = stash[LS::Q + q][tid];
+          });
+        },
+        p, gb, pb, bi);
+  } else if constexpr (MODEL == 0 || MODEL == 2)
     vjp_cumulant27<LS, LES, CT>(fg, ph, lg[0], lp[0], p, gb, pb, bc, bi);
   else
     vjp_bgk_q19_q6<LES, CT>(fg, ph, lg[0], lp[0], p, gb, pb, bc, bi);

@@ -280,7 +280,13 @@ int lbm_set_populations(lbm_handle* h, const double* host_f, const double* host_
  * otherwise); LBM_ESTATE if the
  * handle is not at step 0. adj_ws: device scratch of
  * lbm_adjoint_workspace_bytes(cfg, n, k_ckpt) bytes (LBM_ENOMEM if smaller).
- * Leaves the handle at step n. Synchronises. */
+ * When one population buffer is at most 64 MiB (a cache-resident grid whose
+ * kernels are latency bound) and there are two segments or more, the
+ * workspace holds two trajectory sets and the run recomputes segment s - 1 on
+ * a second stream of its own (non-blocking, default priority, made on the
+ * first such run and released by lbm_destroy) while segment s is reversed on
+ * the handle's stream; events order the two, and the second stream is idle
+ * when the call returns. Leaves the handle at step n. Synchronises. */
 size_t lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t n_steps, int64_t k_ckpt);
 int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_front,
                     double w_fw, void* adj_ws, size_t adj_bytes, double* J_out,

@@ -191,7 +191,15 @@ namespace {
 struct AdjLayout {
   size_t buf, ckpt, traj, lam, gpart, fwpart, small, total;
   int64_t nseg, ktraj;
+  bool overlap;  // two trajectory sets: segment s - 1 is recomputed while s is reversed
 };
+
+// A state of at most this size stays in the 256 MB last-level cache with the
+// adjoint buffers, and its kernels are bound by latency, not bandwidth: the
+// adjoint run then recomputes the next segment on a second stream while the
+// reverse sweep runs, so that the two sets of kernels fill each other's
+// stalls. Larger states are bandwidth bound and run both on one stream.
+constexpr size_t kOverlapStateBytes = 64ull << 20;
 
 AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, int64_t k) {
   AdjLayout L;
@@ -203,6 +211,7 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, 
   // a segment's first state is its checkpoint; the trajectory slots hold
   // the other k - 1 (fewer when the run is shorter)
   L.ktraj = (k < n_steps ? k : n_steps) - 1;
+  L.overlap = L.nseg >= 2 && L.buf <= kOverlapStateBytes;
   const int bx = block_x(c->nx);
   const int64_t ablocks = (int64_t)((c->nx + bx - 1) / bx) * c->ny * c->nz;
   const int64_t fblocks = (int64_t)lbm::xblocks(c->nx) * c->ny * std::min(c->nz, 2);
@@ -210,7 +219,7 @@ AdjLayout adj_layout(const lbm_config* c, const lbm_params* p, int64_t n_steps, 
   L.ckpt = off;
   off += (size_t)L.nseg * L.buf;
   L.traj = off;
-  off += (size_t)L.ktraj * L.buf;
+  off += (size_t)(L.overlap ? 2 : 1) * L.ktraj * L.buf;
   L.lam = off;
   off += 2 * L.buf;
   L.gpart = off;
@@ -242,6 +251,30 @@ size_t lbm_adjoint_workspace_bytes(const lbm_config* cfg, int64_t n_steps, int64
   return adj_layout(cfg, &p, n_steps, k_ckpt).total;
 }
 
+// The adjoint run's second stream (non-blocking, default priority) and the
+// events that order it against the handle's stream, made once per handle.
+static int ensure_side_stream(lbm_handle* h) {
+  if (h->side) return LBM_OK;
+  hipStream_t st = nullptr;
+  hipEvent_t ev[5] = {};
+  bool ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; ok && i < 5; ++i)
+    ok = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    for (int i = 0; i < 5; ++i)
+      if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (st) (void)hipStreamDestroy(st);
+    return fail(LBM_EDEVICE, "could not create the adjoint run's second stream");
+  }
+  h->side = st;
+  h->ev_fork = ev[0];
+  h->ev_rec[0] = ev[1];
+  h->ev_rec[1] = ev[2];
+  h->ev_rev[0] = ev[3];
+  h->ev_rev[1] = ev[4];
+  return LBM_OK;
+}
+
 int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_front, double w_fw,
                     void* adj_ws, size_t adj_bytes, double* J_out, double* dJ_dcs,
                     double* dJ_dsct, double* dJ_dchi0_dev) {
@@ -269,17 +302,26 @@ int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_fro
   HIPCHECK(lbm::launch_zero(h, gpart, 2 * (int64_t)nblk));
   HIPCHECK(lbm::launch_zero(h, small, 32));
   // Storage of the forward states. State m of segment s (m0 = s k_ckpt <= m <
-  // e) is checkpoint s when m = m0, else trajectory slot m - m0 (1 .. k - 1).
-  // The forward pass writes every checkpoint state straight into its slot and
-  // the states of the last segment straight into the trajectory, so the
-  // reverse pass recomputes every segment but the last and copies nothing;
-  // the other states go through the handle's two buffers, and the final state
-  // n ends in the handle's current buffer.
-  auto traj_slot = [&](int64_t i) { return (void*)(ws + L.traj + (size_t)(i - 1) * L.buf); };
+  // e) is checkpoint s when m = m0, else slot m - m0 (1 .. k - 1) of the
+  // segment's trajectory set (set s mod 2 when two sets overlap the
+  // recomputation with the reverse sweep, else the one set). The forward
+  // pass writes every checkpoint state straight into its slot and the states
+  // of the last segment straight into their trajectory set, so the reverse
+  // pass recomputes every segment but the last and copies nothing; the other
+  // states go through the handle's two buffers, and the final state n ends in
+  // the handle's current buffer.
+  auto traj_slot = [&](int64_t s, int64_t i) {
+    const size_t set = L.overlap ? (size_t)(s % 2) : 0;
+    return (void*)(ws + L.traj + (set * L.ktraj + (size_t)(i - 1)) * L.buf);
+  };
   auto state_of = [&](int64_t m) {
     const int64_t s = m / k_ckpt, m0 = s * k_ckpt;
-    return m == m0 ? ckpt(s) : traj_slot(m - m0);
+    return m == m0 ? ckpt(s) : traj_slot(s, m - m0);
   };
+  if (L.overlap) {
+    rc = ensure_side_stream(h);
+    if (rc) return rc;
+  }
   const int64_t last = L.nseg - 1;
   // forward; the wall-layer sums of F_w(m), m = 1..n, go to one slot set per
   // step (slot m - 1) and are reduced once, in fixed order, at the end. Step
@@ -308,6 +350,22 @@ int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_fro
     cur = dst;
     h->step += 1;
   }
+  auto recompute = [&](int64_t s, hipStream_t st) -> hipError_t {
+    const int64_t m0 = s * k_ckpt;
+    const int64_t e = std::min<int64_t>(m0 + k_ckpt, n_steps);
+    for (int64_t m = m0; m + 1 < e; ++m) {
+      const hipError_t err = lbm::launch_step(h, state_of(m), state_of(m + 1), fw_spare, st);
+      if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+  };
+  if (L.overlap) {
+    // the second stream starts on segment last - 1 once the forward pass is done
+    HIPCHECK(hipEventRecord(h->ev_fork, h->stream));
+    HIPCHECK(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+    HIPCHECK(recompute(last - 1, h->side));
+    HIPCHECK(hipEventRecord(h->ev_rec[(last - 1) % 2], h->side));
+  }
   HIPCHECK(lbm::launch_fw_layers(h, h->buf[h->cur], fwpart + 2 * (size_t)fwb * (n_steps - 1)));
   HIPCHECK(lbm::launch_fw_reduce(h, fwpart, n_steps * fwb, small));
   // final state: front and its seed, lambda(n)
@@ -319,20 +377,34 @@ int lbm_adjoint_run(lbm_handle* h, int64_t n_steps, int64_t k_ckpt, double w_fro
   void* lam_out = ws + L.lam + L.buf;
   HIPCHECK(lbm::launch_adjoint_seed(h, h->buf[h->cur], lam_next, a0, a1, small + 8));
   // reverse sweep over the segments, recomputing each from its checkpoint
-  // (the last segment's states are still in the trajectory)
+  // (the last segment's states are still in the trajectory). With two
+  // trajectory sets the second stream recomputes segment s - 1 (event
+  // ev_rec[(s - 1) % 2]) while this stream reverses segment s, and it starts
+  // on segment s - 2, whose set is s's, only once s is reversed (ev_rev[s % 2]).
   for (int64_t s = last; s >= 0; --s) {
     const int64_t m0 = s * k_ckpt;
     const int64_t e = std::min<int64_t>(m0 + k_ckpt, n_steps);
-    if (s != last)
-      for (int64_t m = m0; m + 1 < e; ++m)
-        HIPCHECK(lbm::launch_step(h, state_of(m), state_of(m + 1), fw_spare));
+    if (s != last) {
+      if (L.overlap)
+        HIPCHECK(hipStreamWaitEvent(h->stream, h->ev_rec[s % 2], 0));
+      else
+        HIPCHECK(recompute(s, h->stream));
+    }
     for (int64_t m = e - 1; m >= m0; --m) {
       const bool seed = m >= 1;
       HIPCHECK(lbm::launch_adjoint_step(h, state_of(m), lam_next, lam_out, seed ? a0 : 0.0,
                                         seed ? a1 : 0.0, gpart, m == 0 ? dJ_dchi0_dev : nullptr));
       std::swap(lam_next, lam_out);
     }
+    if (L.overlap && s >= 2) {
+      HIPCHECK(hipEventRecord(h->ev_rev[s % 2], h->stream));
+      HIPCHECK(hipStreamWaitEvent(h->side, h->ev_rev[s % 2], 0));
+      HIPCHECK(recompute(s - 2, h->side));
+      HIPCHECK(hipEventRecord(h->ev_rec[s % 2], h->side));
+    }
   }
+  // every recomputation on the second stream ended before a reverse step of
+  // this stream that waited for it, the last one (segment 0) before step 0
   HIPCHECK(lbm::launch_sum_pairs(h, gpart, nblk, small + 16));
   double hs[32], r[8];
   HIPCHECK(hipMemcpyAsync(hs, small, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
@@ -419,6 +491,18 @@ int lbm_create(const lbm_config* cfg, void* dev_workspace, size_t bytes, void* h
 }
 
 int lbm_destroy(lbm_handle* h) {
+  if (h && h->side) {
+    // the adjoint run's second stream is idle: every run ends with a
+    // synchronisation of the handle's stream, which waited for it
+    if (hipSetDevice(h->device) == hipSuccess) {
+      (void)hipEventDestroy(h->ev_fork);
+      for (int i = 0; i < 2; ++i) {
+        (void)hipEventDestroy(h->ev_rec[i]);
+        (void)hipEventDestroy(h->ev_rev[i]);
+      }
+      (void)hipStreamDestroy(h->side);
+    }
+  }
   delete h;
   return LBM_OK;
 }

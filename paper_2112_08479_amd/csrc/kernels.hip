@@ -615,7 +615,7 @@ static int cumulant_kind(const lbm_handle* h) {
 
 template <int M, typename ST, typename SS, typename CT, int NPT>
 static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src, void* dst,
-                                  double* fw) {
+                                  double* fw, hipStream_t st) {
   const bool les = h->cfg.cs_smag > 0.0;
   const int per_thread_x = (g.nx + NPT - 1) / NPT;  // x-extent in threads if one block
   const int bx = per_thread_x >= kBlock ? kBlock : ((per_thread_x + 63) / 64) * 64;
@@ -630,14 +630,14 @@ static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src,
       if (kind == kCumGeneral) return hipErrorInvalidValue;
       if constexpr (M != 1) {
         if (kind == kCumParam) {
-          hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumParam, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, fw);
+          hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumParam, NPT, true>), dim3(blocks), dim3(bx), 0, st, s, d, g, p, nbx, fw);
           return hipGetLastError();
         }
       }
       if (les)
-        hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, fw);
+        hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT, true>), dim3(blocks), dim3(bx), 0, st, s, d, g, p, nbx, fw);
       else
-        hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT, true>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, fw);
+        hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT, true>), dim3(blocks), dim3(bx), 0, st, s, d, g, p, nbx, fw);
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
@@ -645,22 +645,22 @@ static hipError_t launch_step_npt(lbm_handle* h, const Grid& g, const void* src,
   }
   if constexpr (M == 1) {  // BGK: one collision kind
     if (les)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, st, s, d, g, p, nbx, nullptr);
     else
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, st, s, d, g, p, nbx, nullptr);
   } else {
     // the parametrised kind never has the LES (rejected when the handle is made)
     const int kind = cumulant_kind(h);
     if (les && kind == kCumGeneral)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, st, s, d, g, p, nbx, nullptr);
     else if (les)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, true, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, st, s, d, g, p, nbx, nullptr);
     else if (kind == kCumParam)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumParam, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumParam, NPT>), dim3(blocks), dim3(bx), 0, st, s, d, g, p, nbx, nullptr);
     else if (kind == kCumGeneral)
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumGeneral, NPT>), dim3(blocks), dim3(bx), 0, st, s, d, g, p, nbx, nullptr);
     else
-      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, h->stream, s, d, g, p, nbx, nullptr);
+      hipLaunchKernelGGL((k_step<M, ST, SS, CT, false, kCumFast, NPT>), dim3(blocks), dim3(bx), 0, st, s, d, g, p, nbx, nullptr);
   }
   return hipGetLastError();
 }
@@ -673,8 +673,10 @@ static bool few_waves(const lbm_handle* h, int npt) {
   return waves < (int64_t)16 * h->cu_count;
 }
 
-hipError_t launch_step(lbm_handle* h, const void* src, void* dst, double* fw) {
+hipError_t launch_step(lbm_handle* h, const void* src, void* dst, double* fw,
+                       hipStream_t stream) {
   const Grid g = grid_of(h);
+  if (!stream) stream = h->stream;
   return with_model(h, [&](auto mc) {
     constexpr int M = decltype(mc)::value;
     return with_storage(h, [&](auto st, auto ss, auto ct) {
@@ -683,9 +685,9 @@ hipError_t launch_step(lbm_handle* h, const void* src, void* dst, double* fw) {
       using CT = decltype(ct);
       constexpr int NPT = nodes_per_thread<M, ST>();
       if constexpr (NPT > 1) {
-        if (few_waves(h, NPT)) return launch_step_npt<M, ST, SS, CT, 1>(h, g, src, dst, fw);
+        if (few_waves(h, NPT)) return launch_step_npt<M, ST, SS, CT, 1>(h, g, src, dst, fw, stream);
       }
-      return launch_step_npt<M, ST, SS, CT, NPT>(h, g, src, dst, fw);
+      return launch_step_npt<M, ST, SS, CT, NPT>(h, g, src, dst, fw, stream);
     });
   });
 }

@@ -32,6 +32,10 @@ struct lbm_handle {
   bool initialised;
   int x0;             // gate index
   int diag_blocks;
+  // the adjoint run's second stream (default priority) and its events, made
+  // on first use for a grid whose recomputation overlaps the reverse sweep
+  hipStream_t side;
+  hipEvent_t ev_fork, ev_rec[2], ev_rev[2];
 };
 
 namespace lbm {
@@ -51,8 +55,10 @@ constexpr int kDiagSlots = 8;  // partial sums per diagnostic block
 // kernels.hip
 // one step src -> dst; fw (the adjoint's forward pass, FP32 / FP64 storage):
 // also the wall-layer sums of F_w of the gathered state into
-// fw[2 fw_blocks], as launch_fw_layers writes them
-hipError_t launch_step(lbm_handle* h, const void* src, void* dst, double* fw = nullptr);
+// fw[2 fw_blocks], as launch_fw_layers writes them. st: the stream to launch
+// on (null: the handle's)
+hipError_t launch_step(lbm_handle* h, const void* src, void* dst, double* fw = nullptr,
+                       hipStream_t st = nullptr);
 hipError_t launch_init_lock(lbm_handle* h, double lock_fraction, double amp, uint64_t seed);
 hipError_t launch_init_field(lbm_handle* h, const double* chi0);
 hipError_t launch_moments(lbm_handle* h, int dtype, void* rho, void* ux, void* uy, void* uz,

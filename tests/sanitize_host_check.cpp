@@ -11,7 +11,7 @@
 #include "runtime.h"
 
 namespace lbm {
-hipError_t launch_step(lbm_handle*, const void*, void*, double*) { return hipErrorNoDevice; }
+hipError_t launch_step(lbm_handle*, const void*, void*, double*, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_init_lock(lbm_handle*, double, double, uint64_t) { return hipErrorNoDevice; }
 hipError_t launch_init_field(lbm_handle*, const double*) { return hipErrorNoDevice; }
 hipError_t launch_moments(lbm_handle*, int, void*, void*, void*, void*, void*) { return hipErrorNoDevice; }

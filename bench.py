@@ -66,8 +66,10 @@ def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0, par
     differentiated run; the algorithmic bytes are those of the passes made: a
     forward step (2 Q 4 B per node) per step, one per recomputed step, a
     reverse step (3 Q 4 B) per step and one initial copy, Q the populations
-    per node. The workspace is allocated before the timed
-    region; the run is timed with HIP events on the library's stream."""
+    per node. The workspace is allocated before the timed region, and one
+    untimed run of the same size comes first (it loads the kernels and makes
+    the run's second stream); the second run is timed with HIP events on the
+    library's stream."""
     import torch
 
     import paper_2112_08479_amd as pkg
@@ -77,10 +79,12 @@ def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0, par
     else:
         cfg = pkg.Config(nx, ny, nz, model=model, storage=pkg.F32, re_b=1000.0, cs_smag=0.1, sc_t=1.0)
     lat = pkg.Lattice(cfg)
-    lat.init_lock_exchange(0.125, 1e-3, 0)
     # workspace and gradient buffer allocated before the timed region
     ws = torch.empty(lat.adjoint_workspace_bytes(n_steps, k_ckpt), dtype=torch.uint8, device="cuda")
     gchi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+    lat.init_lock_exchange(0.125, 1e-3, 0)
+    lat.adjoint_run(n_steps, k_ckpt, ws=ws, gchi=gchi)  # warm-up
+    lat.init_lock_exchange(0.125, 1e-3, 0)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(lat.stream)
@@ -106,8 +110,8 @@ def measure_adjoint(nx=256, ny=16, nz=32, n_steps=2000, k_ckpt=100, model=0, par
             "nodes": n, "steps": n_steps, "recomputed_steps": recomputed, "seconds": dt, "MNUPS": mnups,
             "bytes_per_node_update": bpn, "GB_per_s": mnups * 1e6 * bpn / 1e9,
             "J": J, "dJ_dcs": dcs, "dJ_dsct": dsct, "hbm_frac": mnups * 1e6 * bpn / 1e9 / HBM_PEAK_GBS,
-            "note": ("state fits the 256 MB last-level cache and the run is launch bound: not an HBM "
-                     "roofline case" if n * q * 4 < (256 << 20) else "HBM resident")}
+            "note": ("state fits the 256 MB last-level cache and the run is bound by the kernels' "
+                     "latency: not an HBM roofline case" if n * q * 4 < (256 << 20) else "HBM resident")}
 
 
 # adjoint runs: the 256 x 16 x 32 workload (2000 steps, checkpoints every 100)

@@ -494,6 +494,8 @@ int lbm_destroy(lbm_handle* h) {
   if (h && h->side) {
     // the adjoint run's second stream is idle: every run ends with a
     // synchronisation of the handle's stream, which waited for it
+    int prev = -1;
+    const bool had = hipGetDevice(&prev) == hipSuccess;
     if (hipSetDevice(h->device) == hipSuccess) {
       (void)hipEventDestroy(h->ev_fork);
       for (int i = 0; i < 2; ++i) {
@@ -501,6 +503,7 @@ int lbm_destroy(lbm_handle* h) {
         (void)hipEventDestroy(h->ev_rev[i]);
       }
       (void)hipStreamDestroy(h->side);
+      if (had && prev != h->device) (void)hipSetDevice(prev);
     }
   }
   delete h;

@@ -19,7 +19,8 @@ Recorded:
     numpy's generator from seed 3.
 
 Run: python tests/golden/make_benchmark_grid_fixture.py [model ...]
-(about 1.5 hours per model on 8 cores; peak memory about 10 GB).
+(on 8 cores: about 3.5 hours for model 0, whose collision the oracle takes
+through the cumulant ring, and 6 minutes for model 1; peak memory about 10 GB).
 """
 import json
 import os

@@ -1,5 +1,12 @@
 """Parity at the benchmark sizes and the precision report.
 
+* 1024 x 64 x 128, 100 steps from the lock-exchange start (Re_b = 30000,
+  C_s = 0.1, Sc_T = 1; models 1 and 2): the GPU against fixtures the FP64
+  oracle wrote for the whole grid (tests/golden/make_benchmark_grid_fixture.py,
+  which calls only the oracle): rho, u and chi at sampled nodes (walls, gate,
+  span edges, random interior) within 1e-5 of each field's norm for FP32
+  storage (1e-10 for FP64), and the diagnostics.
+
 * 1024 x 64 x 128 (every model, FP32 and FP64, the launch configuration
   bench.py times): after 20 steps of the lock exchange, one more step is
   compared with the oracle at sampled nodes -- gate columns, every wall, the
@@ -15,6 +22,9 @@
 * The same storage modes against FP32 storage at 2048 x 128 x 256, 2000
   steps: the front within 1 % for FP16 and BF16-flow + FP16-scalar.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -267,3 +277,42 @@ def test_16bit_storage_of_the_parametrised_model3():
         assert rows[name]["nonfinite"] == 0
         assert rows[name]["front_rel_diff"] <= 0.01
         assert abs(rows[name]["chi_mass_drift"]) < 0.01
+
+
+GOLDEN_DIR = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("storage,tol", [(pkg.F32, 1e-5), (pkg.F64, 1e-10)], ids=["f32", "f64"])
+@pytest.mark.parametrize("model", [0, 1])
+def test_benchmark_grid_100_steps_against_the_oracle(model, storage, tol):
+    with open(os.path.join(GOLDEN_DIR, f"benchmark_grid_100steps_model{model}.json")) as fh:
+        ref = json.load(fh)
+    case = dict(ref["case"])
+    assert case.pop("model") == model
+    lat = pkg.Lattice(pkg.Config(storage=storage, model=model, **case))
+    lat.init_lock_exchange(ref["lock_fraction"], ref["noise_amp"], ref["seed"])
+    lat.step(ref["steps"])
+    got = gpu_moments(lat)
+    d = lat.diagnostics()
+    lat.close()
+    k, j, i = (np.array(c) for c in zip(*ref["nodes"]))
+    nrm = ref["norms"]
+    scale = {"rho": nrm["drho"], "ux": nrm["umag"], "uy": nrm["umag"], "uz": nrm["umag"], "chi": nrm["chi"]}
+    own = {"rho": nrm["drho"], "ux": nrm["ux"], "uy": nrm["uy"], "uz": nrm["uz"], "chi": nrm["chi"]}
+    errs, errs_own = {}, {}
+    for f in ("rho", "ux", "uy", "uz", "chi"):
+        e = np.abs(got[f][k, j, i] - np.array(ref[f])).max()
+        errs[f] = float(e / scale[f])
+        errs_own[f] = float(e / own[f]) if own[f] > 0 else float(e)
+    od = ref["diagnostics"]
+    print(f"model {model} storage {storage}: {len(k)} nodes, errors {errs}; per own component norm "
+          f"{errs_own}; x_front {d['x_front']} vs {od['x_front']}, mass {d['mass']} vs {od['mass']}, "
+          f"F_w {d['fw']} vs {od['fw']}", flush=True)
+    assert max(errs.values()) < tol, errs
+    assert abs(d["mass"] - od["mass"]) <= tol * 1e-3 * od["mass"]
+    assert abs(d["chi_mass"] - od["chi_mass"]) <= tol * od["chi_mass"]
+    assert abs(d["x_front"] - od["x_front"]) <= tol * od["x_front"]
+    fw_scale = lat.params["nu0"] * 3.0 * nrm["umag"] * case["nx"] * case["ny"]
+    assert abs(d["fw"] - od["fw"]) <= tol * fw_scale
+    assert d["nonfinite"] == 0

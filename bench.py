@@ -300,7 +300,7 @@ def main():
                     help="only the differentiation form: one adjoint run per JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("the library runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"

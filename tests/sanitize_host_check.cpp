@@ -80,7 +80,7 @@ int main() {
         } else {
           EXPECT(lbm_adjoint_workspace_bytes(&c, 100, 10) == 0);
         }
-        // lbm_create: no GPU in this build's stubs or runtime, or a null
+        // lbm_create: no GPU behind the stubbed launchers or the runtime, or a null
         // workspace: never a handle
         lbm_handle* h = (lbm_handle*)0x1;
         const int rc = lbm_create(&c, nullptr, 0, nullptr, &h);

@@ -380,9 +380,15 @@ __global__ __launch_bounds__(1024) void k_diag_final(const double* __restrict__ 
   const double theta = 0.02;
   int best = -1;
   for (int i = t; i < g.nx; i += blockDim.x) {
-    double m = -INFINITY;
-    for (int k = 0; k < g.nz; ++k) m = fmax(m, chibar[(int64_t)k * g.nx + i]);
-    if (m >= theta) best = i;
+    // the depth maximum of column i, in four independent chains so that
+    // the loads overlap (max is exact: the order does not matter)
+    double m[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    int k = 0;
+    for (; k + 3 < g.nz; k += 4)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) m[j] = fmax(m[j], chibar[(int64_t)(k + j) * g.nx + i]);
+    for (; k < g.nz; ++k) m[0] = fmax(m[0], chibar[(int64_t)k * g.nx + i]);
+    if (fmax(fmax(m[0], m[1]), fmax(m[2], m[3])) >= theta) best = i;
   }
   for (int k = 0; k < 6; ++k) v[k] = (k == 4) ? wave_max(v[k]) : wave_sum(v[k]);
   for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
@@ -391,23 +397,30 @@ __global__ __launch_bounds__(1024) void k_diag_final(const double* __restrict__ 
     ired[wid] = best;
   }
   __syncthreads();
-  if (t == 0) {
-    const int nw = blockDim.x >> 6;
-    for (int w = 1; w < nw; ++w) {
-      for (int k = 0; k < 6; ++k) v[k] = (k == 4) ? fmax(v[k], red[w * 6 + k]) : v[k] + red[w * 6 + k];
-      best = max(best, ired[w]);
+  if (wid != 0) return;
+  // wave 0: the sums in fixed order (lane 0), then the depth maxima of the
+  // front column and its neighbour across the wave
+  const int nw = blockDim.x >> 6;
+  for (int w = 1; w < nw; ++w) {
+    for (int k = 0; k < 6; ++k) v[k] = (k == 4) ? fmax(v[k], red[w * 6 + k]) : v[k] + red[w * 6 + k];
+    best = max(best, ired[w]);
+  }
+  double m0 = -INFINITY, m1 = -INFINITY;
+  if (best >= 0 && best < g.nx - 1) {
+    for (int k = lane; k < g.nz; k += 64) {
+      m0 = fmax(m0, chibar[(int64_t)k * g.nx + best]);
+      m1 = fmax(m1, chibar[(int64_t)k * g.nx + best + 1]);
     }
+  }
+  m0 = wave_max(m0);
+  m1 = wave_max(m1);
+  if (lane == 0) {
     double xf;
     if (best < 0) {
       xf = 0.0;
     } else if (best == g.nx - 1) {
       xf = (double)g.nx;
     } else {
-      double m0 = -INFINITY, m1 = -INFINITY;
-      for (int k = 0; k < g.nz; ++k) {
-        m0 = fmax(m0, chibar[(int64_t)k * g.nx + best]);
-        m1 = fmax(m1, chibar[(int64_t)k * g.nx + best + 1]);
-      }
       xf = best + 0.5 + (m0 - theta) / (m0 - m1);
     }
     out[0] = (double)g.n + v[0];

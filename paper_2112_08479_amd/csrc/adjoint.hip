@@ -100,8 +100,9 @@ __global__ __launch_bounds__(kBlock) void k_adjoint_step(const ST* __restrict__ 
   CT bc = CT(0), bi = CT(0);
   if constexpr ((MODEL == 0 || MODEL == 2) && PARAM) {
     // the scalar populations and their adjoints wait in LDS, each thread in
-    // its own column, while the flow's reverse sweep runs (the adjoint
-    // above takes them last): that keeps the kernel at two waves per SIMD
+    // its own column, while the flow's reverse sweep runs
+    // (vjp_cumulant27_param takes the scalar part last): that keeps the FP32
+    // model-3 kernel at two waves per SIMD
     __shared__ CT stash[2 * LS::Q][kBlock];
     const int tid = (int)threadIdx.x;
     const CT chi = scalar_sum<LS>(ph);

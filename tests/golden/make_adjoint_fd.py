@@ -1,7 +1,7 @@
 """Writes FP64 central finite differences of the adjoint objective
 J = x_f(n) + (1/n) sum_{m=1..n} F_w(m), computed by the oracle only.
 
-Two cases (the lock exchange, D3Q27 cumulant + D3Q7, Re_b = 1000, C_s = 0.1,
+Three cases (the lock exchange, D3Q27 cumulant + D3Q7, Re_b = 1000, C_s = 0.1,
 Sc_T = 1, g' = 1e-4, gate noise 1e-3 with seed 0):
 
 * ``small`` -> adjoint_fd_128x8x16.json: 128 x 8 x 16, 500 steps.
@@ -14,8 +14,12 @@ Sc_T = 1, g' = 1e-4, gate noise 1e-3 with seed 0):
   the differentiated benchmark run). d/dC_s and d/dSc_T only, each from two
   2000-step runs. The five runs (J and the four shifted ones) go to parallel
   worker processes; about three hours on 8 cores.
+* ``c3_chi0`` -> adjoint_fd_256x16x32_chi0.json: the same run, directional
+  derivatives along two seeded random chi0 directions of unit infinity norm
+  (tests/inputs.random_field, seeds 21 and 22, values in [-1, 1]); four
+  2000-step runs, about two hours on 8 cores with 4 workers.
 
-Run: python tests/golden/make_adjoint_fd.py [small|c3] [workers]
+Run: python tests/golden/make_adjoint_fd.py [small|c3|c3_chi0] [workers]
 """
 import json
 import os
@@ -41,6 +45,8 @@ CASES = {
                   dir_seeds=(11, 12), nodes=((3, 2, 15), (8, 5, 16))),  # (k, j, i) next to the gate
     "c3": dict(grid=dict(nx=256, ny=16, nz=32), steps=2000, out="adjoint_fd_256x16x32.json",
                dir_seeds=(), nodes=()),
+    "c3_chi0": dict(grid=dict(nx=256, ny=16, nz=32), steps=2000, out="adjoint_fd_256x16x32_chi0.json",
+                    dir_seeds=(21, 22), nodes=(), params=False),
 }
 
 
@@ -79,9 +85,12 @@ def main():
     cs0, sct0 = kw["cs_smag"], kw["sc_t"]
     shape = (kw["nz"], kw["ny"], kw["nx"])
     dirs = directions(shape, case["dir_seeds"], case["nodes"])
-    runs = [(kw, steps, cs0, sct0, None, 0.0, threads),
-            (kw, steps, cs0 + H, sct0, None, 0.0, threads), (kw, steps, cs0 - H, sct0, None, 0.0, threads),
-            (kw, steps, cs0, sct0 + H, None, 0.0, threads), (kw, steps, cs0, sct0 - H, None, 0.0, threads)]
+    params = case.get("params", True)
+    runs = []
+    if params:
+        runs = [(kw, steps, cs0, sct0, None, 0.0, threads),
+                (kw, steps, cs0 + H, sct0, None, 0.0, threads), (kw, steps, cs0 - H, sct0, None, 0.0, threads),
+                (kw, steps, cs0, sct0 + H, None, 0.0, threads), (kw, steps, cs0, sct0 - H, None, 0.0, threads)]
     for d in dirs:
         runs += [(kw, steps, cs0, sct0, d, H, threads), (kw, steps, cs0, sct0, d, -H, threads)]
     t0 = time.time()
@@ -92,9 +101,12 @@ def main():
         js = [_objective(r) for r in runs]
     print(f"{len(runs)} runs in {time.time() - t0:.0f} s", flush=True)
     res = {"case": kw, "steps": steps, "h": H, "dir_seeds": list(case["dir_seeds"]),
-           "nodes": [list(n) for n in case["nodes"]], "J": js[0],
-           "dJ_dcs": (js[1] - js[2]) / (2 * H), "dJ_dsct": (js[3] - js[4]) / (2 * H),
-           "dJ_dchi0_dir": [(js[5 + 2 * i] - js[6 + 2 * i]) / (2 * H) for i in range(len(dirs))]}
+           "nodes": [list(n) for n in case["nodes"]]}
+    o = 0
+    if params:
+        res.update(J=js[0], dJ_dcs=(js[1] - js[2]) / (2 * H), dJ_dsct=(js[3] - js[4]) / (2 * H))
+        o = 5
+    res["dJ_dchi0_dir"] = [(js[o + 2 * i] - js[o + 1 + 2 * i]) / (2 * H) for i in range(len(dirs))]
     print(json.dumps(res), flush=True)
     with open(os.path.join(HERE, case["out"]), "w") as fh:
         json.dump(res, fh, indent=1)

@@ -9,11 +9,11 @@
   tests/golden/make_adjoint_fd.py, which calls only the oracle): FP64 to 1e-5,
   FP32 to 1e-3 relative.
 * 256 x 16 x 32, 2000 steps, checkpoints every 100 (the benchmark adjoint):
-  dJ/dC_s and dJ/dSc_T against the oracle's FP64 central differences at that
-  size (tests/golden/adjoint_fd_256x16x32.json, same script), FP64 to 1e-5
-  and FP32 to 1e-3 relative; and, for directions of chi0 too, the adjoint
-  gradient against central differences (h = 1e-4) of the library's own FP64
-  forward map to 1e-3 relative.
+  dJ/dC_s, dJ/dSc_T and two chi0 directions against the oracle's FP64
+  central differences at that size (tests/golden/adjoint_fd_256x16x32.json
+  and adjoint_fd_256x16x32_chi0.json, same script), FP64 to 1e-5 and FP32 to
+  1e-3 relative; and the adjoint gradient against central differences
+  (h = 1e-4) of the library's own FP64 forward map to 1e-3 relative.
 """
 import dataclasses
 import json
@@ -32,6 +32,7 @@ from tests import inputs
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_128x8x16.json")
 GOLDEN_C3 = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_256x16x32.json")
+GOLDEN_C3_CHI0 = os.path.join(os.path.dirname(__file__), "golden", "adjoint_fd_256x16x32_chi0.json")
 
 
 def _gpu_grad(kw, storage, chi0, n, k, w_front=1.0, w_fw=1.0):
@@ -150,6 +151,23 @@ def test_full_size_adjoint_matches_oracle_finite_differences(storage, tol):
     assert abs(J - ref["J"]) <= (1e-9 if storage == pkg.F64 else 1e-5) * abs(ref["J"])
     assert abs(dcs - ref["dJ_dcs"]) <= tol * abs(ref["dJ_dcs"])
     assert abs(dsct - ref["dJ_dsct"]) <= tol * abs(ref["dJ_dsct"])
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("storage,tol", [(pkg.F64, 1e-5), (pkg.F32, 1e-3)], ids=["f64", "f32"])
+def test_full_size_adjoint_chi0_directions_match_oracle_finite_differences(storage, tol):
+    with open(GOLDEN_C3_CHI0) as fh:
+        ref = json.load(fh)
+    kw = ref["case"]
+    chi0 = olbm.chi0_lock_exchange(OConfig(**kw), 0.125, 1e-3, 0)
+    _, _, _, g = _gpu_grad(kw, storage, chi0, ref["steps"], 100)
+    got = []
+    for s in ref["dir_seeds"]:
+        d = inputs.random_field(tuple(chi0.shape), s, -1.0, 1.0)
+        got.append(float((g * (d / np.abs(d).max())).sum()))
+    print(f"storage {storage}: dirs {got} vs {ref['dJ_dchi0_dir']}", flush=True)
+    for a, b in zip(got, ref["dJ_dchi0_dir"]):
+        assert abs(a - b) <= tol * abs(b)
 
 
 @pytest.mark.timeout(900)
